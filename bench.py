@@ -1,0 +1,164 @@
+"""Throughput of the fused ERI + compression path on one MI355X.
+
+A step computes every quartet of the workload once: contracted Cartesian ERIs
+of all 256 classes (s-f on each centre) with the per-quartet n-bit compression
+of eqs. 9-10 fused in (codes and scales written to HBM).  The metric is GERIS:
+1e9 compressed ERIs per second.  Inputs (the plan's pair tables) are resident
+in HBM before the timed region.
+
+Default workload: all 256 classes, 65536 quartets per class, K uniform in
+{1,2,3} per shell, centres uniform in a 10 Bohr cube, exponents log-uniform in
+[0.1, 100], coefficients uniform in [0.1, 1]; FP64 recurrences, int16 codes.
+
+Prints one JSON line (rank 0, N = 1).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GERIS (1e9 ERIs/s) incl. int16 compression, FP64 vs FP32-mixed, + fwd+grad"
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector FP64 / FP32 (published)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(qpc, classes):
+    from paper_2303_13632_amd import workloads as W
+    parts = [W.class_case(cid, n_quartets=qpc) for cid in classes]
+    return W.merge(parts)
+
+
+def cpu_baseline(classes, seconds):
+    """The oracle on a bounded sample of the same workload (first quartets of
+    every class), all host threads.  Returns a dict for the JSON line."""
+    import oracle as O
+    from paper_2303_13632_amd import workloads as W
+    threads = os.cpu_count() or 1
+
+    def run(n):
+        sh, q = W.merge([W.class_case(cid, n_quartets=n) for cid in classes])
+        t0 = time.perf_counter()
+        v, _, sizes = O.eri(sh, q, n_threads=threads)
+        return time.perf_counter() - t0, int(sizes.sum()), len(q)
+
+    t, neri, nq = run(1)
+    n = max(1, min(512, int(seconds / max(t, 1e-3))))
+    if n > 1:
+        t, neri, nq = run(n)
+    return {"value": neri / t / 1e9, "unit": "GERIS", "cores": threads, "kind": "oracle",
+            "sample": "first %d quartets of each of the %d classes of the same workload (%d quartets, %d ERIs), "
+                      "%.1f s, FP64 uncompressed, Rys quadrature, OpenMP over quartets" % (n, len(classes), nq, neri, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--bits", type=int, default=16)
+    ap.add_argument("--quartets-per-class", type=int, default=65536)
+    ap.add_argument("--classes", default="all", help="'all' or comma-separated class ids")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build measures one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2303_13632_amd import eri
+
+    classes = list(range(256)) if args.classes == "all" else [int(c) for c in args.classes.split(",")]
+    t0 = time.time()
+    shells, quartets = build_workload(args.quartets_per_class, classes)
+    log("workload: %d quartets, %d shells (%.1fs)" % (len(quartets), len(shells["L"]), time.time() - t0))
+    t0 = time.time()
+    plan = eri.Plan(shells, quartets, precision=args.precision, bits=args.bits, device=0)
+    del shells, quartets
+    log("plan: %d ERIs, %d primitive quartets, %.1f GB on device (%.1fs)"
+        % (plan.n_eri, plan.n_prim_quartets, plan.device_bytes / 1e9, time.time() - t0))
+    _, codes, scales = plan.alloc(eri=False, codes=True)
+    stream = torch.cuda.current_stream()
+    active = [c for c in classes if plan.class_quartets[c] > 0]
+
+    def step(events=None):
+        for i, c in enumerate(active):
+            if events is not None:
+                events[i][0].record(stream)
+            plan.compute_class(c, None, codes, scales, stream=stream)
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in active]
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(ev[k])
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    per_class_ms = np.array([[ev[k][i][0].elapsed_time(ev[k][i][1]) for i in range(len(active))]
+                             for k in range(args.steps)]).mean(axis=0)
+    geris = plan.n_eri / (ms_step / 1e3) / 1e9
+
+    # roofline of the dominant kernel (the class with the largest time per step)
+    dom = int(np.argmax(per_class_ms))
+    c_dom = active[dom]
+    t_dom = per_class_ms[dom] / 1e3
+    achieved = plan.class_flops[c_dom] / t_dom / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    from paper_2303_13632_amd import workloads as W
+    roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": None, "kernel": "eri_%s_c%03d" % (args.precision, c_dom),
+            "class": "[%d%d|%d%d]" % W.class_of(c_dom), "avg_ms": per_class_ms[dom],
+            "algorithmic_flops_per_launch": plan.class_flops[c_dom]}
+    total_flops = float(sum(plan.class_flops[c] for c in active))
+    if args.per_class_out:
+        rows = []
+        for i, c in enumerate(active):
+            n_eri_c = int(plan.class_eri_off[c + 1] - plan.class_eri_off[c])
+            rows.append({"class": c, "L": W.class_of(c), "ms": per_class_ms[i], "n_eri": n_eri_c,
+                         "geris": n_eri_c / (per_class_ms[i] / 1e3) / 1e9,
+                         "tflops": plan.class_flops[c] / (per_class_ms[i] / 1e3) / 1e12})
+        with open(args.per_class_out, "w") as f:
+            json.dump(rows, f, indent=1)
+
+    out = {
+        "metric": METRIC, "value": geris, "unit": "GERIS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
+                               "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, int%d per-quartet compression"
+                               % (len(active), args.quartets_per_class, args.precision, args.bits),
+                   "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
+                   "n_prim_quartets": int(plan.n_prim_quartets), "precision": args.precision, "bits": args.bits},
+        "whole_step_tflops": total_flops / (ms_step / 1e3) / 1e12,
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(active, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

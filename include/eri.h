@@ -1,0 +1,141 @@
+/*
+ * eri.h -- C ABI of the MI355X library for contracted Cartesian electron
+ * repulsion integrals (ERIs) fused with n-bit fixed-point compression.
+ *
+ * The operations follow Wu et al., "Computing and Compressing Electron
+ * Repulsion Integrals on FPGAs" (arXiv:2303.13632):
+ *   - the ERI [ab|cd] of four Cartesian Gaussian shells (Sec. II-A, eq. 1;
+ *     Sec. II-B, eqs. 2-3), for all 256 classes with s, p, d, f on each centre;
+ *   - the compression of each quartet's ERIs (Sec. II-D): b_max = max |x| over
+ *     the quartet, eps = b_max / (2^(n-1) - 1) (eq. 9), codes
+ *     ANINT(x / eps) (eq. 10), decompression q * eps (eq. 11).
+ * The ERIs are computed on the GPU with the Boys function, the Obara-Saika
+ * vertical and Head-Gordon-Pople horizontal recurrences (the scheme family the
+ * paper cites in Sec. II-C) and primitive contraction.
+ *
+ * Conventions
+ *   Shells: arrays of length n_shells, in host memory, copied at plan time:
+ *     L[s] in 0..3, K[s] in 1..ERI_MAX_K primitives, centre xyz[3s..3s+2]
+ *     (Bohr), primitives exps/coefs[prim_off[s] .. prim_off[s] + K[s]).
+ *     A contracted function is sum_k coefs[k] N(exps[k], L) g(exps[k]) with the
+ *     normalisation N of eq. 1 (axis-aligned component normalised) and no
+ *     renormalisation of the contraction.
+ *   Quartets: int32 quads (a, b, c, d) of shell indices, host memory.
+ *   Components of a shell: x^L first (lx = L..0, ly = L-lx..0, lz = L-lx-ly).
+ *   Values of a quartet: n_ERIQ = ncart(La) ncart(Lb) ncart(Lc) ncart(Ld)
+ *     values, row-major over (a, b, c, d) components.
+ *   Plan order: quartets sorted by class id (La*64 + Lb*16 + Lc*4 + Ld), then
+ *     by primitive counts; all outputs (FP64 values, codes, scales) are laid
+ *     out in plan order, one block of n_ERIQ values and one scale per quartet.
+ *     eri_plan_layout() gives each user quartet's position.
+ *   Codes: n in [2, 32] bits, stored as int8 (n <= 8), int16 (n <= 16) or
+ *     int32 (n <= 32), one per ERI.
+ *   Device pointers are owned by the caller (e.g. allocated by PyTorch).
+ *   Streams: a hipStream_t passed as void* (NULL = the default stream).
+ *   Launches are asynchronous; execution errors surface at a later call or
+ *   stream synchronisation.  A plan is not thread-safe; distinct plans are
+ *   independent.
+ * Errors: every call returns ERI_OK (0) or a negative ERI_E* code; no
+ *   exception crosses the ABI.  eri_status_string() names a code;
+ *   eri_last_hip_error() returns the HIP error behind the last ERI_EHIP.
+ */
+#ifndef ERI_H
+#define ERI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ERI_OK 0
+#define ERI_EINVAL (-1)        /* bad argument (null pointer, bad index, size) */
+#define ERI_EUNSUPPORTED (-2)  /* L > 3, K > ERI_MAX_K, bits outside [2, 32] */
+#define ERI_ENOMEM (-3)        /* host or device allocation failed */
+#define ERI_EHIP (-4)          /* a HIP runtime call failed */
+#define ERI_ESTATE (-5)        /* call not valid for this plan */
+
+#define ERI_MAX_L 3
+#define ERI_MAX_K 16
+
+#define ERI_FP64 0             /* recurrences in FP64 */
+#define ERI_FP32_MIXED 1       /* VRR/HRR in FP32; Boys, prefactors, contraction in FP64 */
+
+typedef struct eri_plan eri_plan;
+
+typedef struct {
+    int32_t precision;   /* ERI_FP64 or ERI_FP32_MIXED */
+    int32_t bits;        /* code width n of eq. 10: 0 = no codes, else 2..32 */
+    int32_t device;      /* HIP device ordinal */
+    int32_t reserved;
+} eri_plan_opts;
+
+typedef struct {
+    int64_t n_quartets;
+    int64_t n_eri;              /* sum of n_ERIQ over all quartets */
+    int64_t n_pairs;            /* shell pairs kept by the plan */
+    int64_t n_prim_pairs;       /* primitive pairs kept by the plan */
+    int64_t n_prim_quartets;    /* sum over quartets of K_a K_b K_c K_d */
+    int64_t device_bytes;       /* device memory held by the plan */
+    int32_t code_bytes;         /* 0, 1, 2 or 4 */
+    int32_t bits;
+    int64_t class_quartets[256];  /* quartets per class */
+    int64_t class_eri_off[257];   /* first ERI of each class in plan order */
+    int64_t class_quartet_off[257];
+    double class_flops[256];      /* algorithmic FLOPs of each class launch */
+} eri_plan_info;
+
+/* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
+ * the host the shell-pair and primitive-pair data the kernels read (Gaussian
+ * product centre, exponent sums, prefactors), sorts the quartets into plan
+ * order and uploads everything to `opts->device`.
+ * Returns ERI_EINVAL for null pointers or indices outside [0, n_shells),
+ * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K] or a bad `bits`,
+ * ERI_ENOMEM / ERI_EHIP on allocation or upload failure.  On success *out owns
+ * all device memory of the plan until eri_plan_destroy(). */
+int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* L, const int32_t* K,
+                    const double* xyz, const int64_t* prim_off, const double* exps,
+                    const double* coefs, const int32_t* quartets, int64_t n_quartets,
+                    const eri_plan_opts* opts);
+
+/* Sizes and per-class layout of the plan's outputs (host struct). */
+int eri_plan_info_get(const eri_plan* plan, eri_plan_info* info);
+
+/* Plan-order layout: for user quartet t, pos[t] is its plan position, so its
+ * values start at eri_off[t] (ERIs) and its scale is scales[pos[t]].  Both
+ * arrays are host memory of length n_quartets. */
+int eri_plan_layout(const eri_plan* plan, int64_t* pos, int64_t* eri_off);
+
+/* Compute every quartet of the plan on `stream` (Sec. II-B..II-D): contracted
+ * ERIs; when out_eri is not NULL they are written as FP64 (n_eri doubles);
+ * when the plan has bits > 0 and out_codes is not NULL, each quartet is
+ * compressed with its own b_max (eqs. 9-10): n_eri codes and n_quartets FP64
+ * scales eps (out_scales, required with codes).  Device pointers, plan order.
+ * Returns ERI_EINVAL if no output is requested. */
+int eri_compute(eri_plan* plan, void* stream, double* out_eri, void* out_codes, double* out_scales);
+
+/* Same as eri_compute for the quartets of one class only (class id
+ * La*64+Lb*16+Lc*4+Ld); pointers address the whole plan-order arrays. */
+int eri_compute_class(eri_plan* plan, int32_t class_id, void* stream, double* out_eri,
+                      void* out_codes, double* out_scales);
+
+/* Standalone compression (eqs. 9-10) of FP64 values on the device: block b is
+ * eri[block_off[b] .. block_off[b+1]) and gets scale scales[b] and codes in the
+ * same positions.  block_off: device int64, n_blocks + 1 entries.
+ * Returns ERI_EUNSUPPORTED for bits outside [2, 32]. */
+int eri_compress(int32_t bits, const double* eri, int64_t n_blocks, const int64_t* block_off,
+                 void* codes, double* scales, void* stream);
+
+/* Decompression (eq. 11): out[i] = codes[i] * scales[b] for i in block b. */
+int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_t n_blocks,
+                   const int64_t* block_off, double* out, void* stream);
+
+void eri_plan_destroy(eri_plan* plan);
+
+const char* eri_status_string(int status);
+int eri_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,746 @@
+"""Generator of the class-specialised HIP kernels.
+
+For each of the 256 classes [ab|cd] (a, b, c, d in s, p, d, f) it writes one
+kernel that computes contracted Cartesian ERIs by
+
+  * the Boys function F_m(T) of each primitive quartet,
+  * the Obara-Saika vertical recurrence (VRR) for [e0|f0]^(m), with e on the
+    bra and f on the ket, |e| in [La, La+Lb] and |f| in [Lc, Lc+Ld],
+  * accumulation of the primitive quartets (contraction) in FP64,
+  * the Head-Gordon-Pople horizontal recurrence (HRR), written in its
+    closed binomial form (b on A, d on C),
+  * the paper's compression (eqs. 9-10): per quartet b_max, eps, n-bit codes.
+
+The paper itself computes with Rys quadrature (its section II-C); the
+recurrences here are the Obara-Saika / Head-Gordon-Pople ones it cites as the
+other family, chosen because they contract before the HRR.
+
+Two work mappings are emitted:
+
+  mode T  one lane computes one contracted quartet; every intermediate is a
+          named register value of straight-line code.
+  mode W  one group of lanes ("slot") computes one quartet: lane l owns one
+          bra index e of [e0|..] (two when a slot would exceed 64 lanes,
+          split by the parity of |e|).  Each lane builds [e0|00]^(m) along
+          its own z->y->x path, then the ket recurrence for all f in
+          registers; the one term of the ket VRR that couples different e,
+          [e-1_i 0|f0]^(m+1), is fetched from the owning lane by a wave
+          permute.  After contraction, each lane applies the ket HRR to its
+          own e, the results go through LDS, and lanes owning ket indices cd
+          apply the bra HRR, reduce b_max and quantise.
+"""
+import itertools
+import math
+import os
+
+REALS = {"fp64": "double", "mixed": "float"}
+
+
+# ---------------------------------------------------------------------------
+# Cartesian bookkeeping
+# ---------------------------------------------------------------------------
+def ncart(L):
+    return (L + 1) * (L + 2) // 2
+
+
+def comps(L):
+    return [(lx, ly, L - lx - ly) for lx in range(L, -1, -1) for ly in range(L - lx, -1, -1)]
+
+
+def cidx(c):
+    L = sum(c)
+    lx, ly = c[0], c[1]
+    return (L - lx) * (L - lx + 1) // 2 + (L - lx - ly)
+
+
+def vadd(a, b):
+    return (a[0] + b[0], a[1] + b[1], a[2] + b[2])
+
+
+def vsub(a, b):
+    return (a[0] - b[0], a[1] - b[1], a[2] - b[2])
+
+
+UNIT = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+ZERO = (0, 0, 0)
+
+
+def lower_dir(v, rule):
+    nz = [i for i in range(3) if v[i] > 0]
+    if rule == "first":
+        return nz[0]
+    if rule == "last":
+        return nz[-1]
+    # largest component, first on ties
+    return max(nz, key=lambda i: (v[i], -i))
+
+
+def class_id(la, lb, lc, ld):
+    return la * 64 + lb * 16 + lc * 4 + ld
+
+
+def class_of(cid):
+    return (cid >> 6) & 3, (cid >> 4) & 3, (cid >> 2) & 3, cid & 3
+
+
+# ---------------------------------------------------------------------------
+# Class plan: orientation, mode and the VRR element sets
+# ---------------------------------------------------------------------------
+class ClassPlan:
+    """Orientation, work mapping and VRR element set of one class.
+
+    `perm` maps computed shells to user shells: the kernel computes
+    [s_perm0 s_perm1 | s_perm2 s_perm3].  Within each pair the shell with the
+    larger L goes first, so the HRR always moves the smaller angular momentum
+    (the canonical ordering of eq. 4); this keeps the HRR short and, with
+    far-apart centres and mixed tight/diffuse exponents, avoids the loss of
+    digits of transferring a high L across a long bond.  The bra/ket order is
+    chosen for the register footprint of mode W."""
+
+    def __init__(self, la, lb, lc, ld, mode=None, perm=None):
+        self.user = (la, lb, lc, ld)
+        self.cid = class_id(la, lb, lc, ld)
+        if perm is None:
+            perm = self._choose_perm()
+        self.perm = tuple(perm)
+        a, b, c, d = (self.user[k] for k in self.perm)
+        self.a, self.b, self.c, self.d = a, b, c, d
+        self.Lab, self.Lcd, self.Ltot = a + b, c + d, a + b + c + d
+        self.E_T = [e for L in range(a, a + b + 1) for e in comps(L)]
+        self.F_T = [f for L in range(c, c + d + 1) for f in comps(L)]
+        self.n_eriq = ncart(la) * ncart(lb) * ncart(lc) * ncart(ld)
+        self.rule = self._best_rule()
+        self.elems = self._closure(self.rule)
+        if mode is None:
+            mode = self._choose_mode()
+        self.mode = mode
+
+    @property
+    def swap(self):
+        return self.perm[0] >= 2
+
+    # ---- orientation ----------------------------------------------------
+    def _choose_perm(self):
+        la, lb, lc, ld = self.user
+        bra = (0, 1) if la >= lb else (1, 0)
+        ket = (2, 3) if lc >= ld else (3, 2)
+
+        def est(lab, lc_, lcd):
+            n_e = (lab + 1) * (lab + 2) * (lab + 3) // 6
+            S = 1 if n_e <= 64 else 2
+            lv = [ncart(k) * (lcd - k + 1) for k in range(lcd + 1)]
+            live = max(sum(lv[max(0, k - 2):k + 1]) for k in range(len(lv)))
+            return S * (live + sum(ncart(x) for x in range(lc_, lcd + 1)))
+
+        keep = est(la + lb, max(lc, ld), lc + ld)
+        swap = est(lc + ld, max(la, lb), la + lb)
+        if swap < keep or (swap == keep and (lc + ld) > (la + lb)):
+            return ket + bra
+        return bra + ket
+
+    # ---- VRR closure (mode T program) ------------------------------------
+    def _closure(self, rule):
+        need = {}
+        stack = [(e, f, 0) for e in self.E_T for f in self.F_T]
+        while stack:
+            el = stack.pop()
+            if el in need:
+                continue
+            e, f, m = el
+            srcs = []
+            if f != ZERO:
+                i = lower_dir(f, rule)
+                fp = vsub(f, UNIT[i])
+                srcs += [(e, fp, m), (e, fp, m + 1)]
+                if fp[i] >= 1:
+                    fpp = vsub(fp, UNIT[i])
+                    srcs += [(e, fpp, m), (e, fpp, m + 1)]
+                if e[i] >= 1:
+                    srcs.append((vsub(e, UNIT[i]), fp, m + 1))
+                need[el] = ("ket", i)
+            elif e != ZERO:
+                i = lower_dir(e, rule)
+                ep = vsub(e, UNIT[i])
+                srcs += [(ep, ZERO, m), (ep, ZERO, m + 1)]
+                if ep[i] >= 1:
+                    epp = vsub(ep, UNIT[i])
+                    srcs += [(epp, ZERO, m), (epp, ZERO, m + 1)]
+                need[el] = ("bra", i)
+            else:
+                need[el] = ("base", None)
+            stack.extend(srcs)
+        return need
+
+    def _best_rule(self):
+        best = None
+        for rule in ("first", "max", "last"):
+            n = len(self._closure(rule))
+            if best is None or n < best[0]:
+                best = (n, rule)
+        return best[1]
+
+    # ---- mode choice -------------------------------------------------------
+    def ket_live_estimate(self):
+        # doubles live per lane in mode W: three consecutive ket levels + accumulators
+        lv = [ncart(k) * (self.Lcd - k + 1) for k in range(self.Lcd + 1)]
+        live = max(sum(lv[max(0, k - 2):k + 1]) for k in range(len(lv)))
+        return live + len(self.F_T)
+
+    def _choose_mode(self):
+        n_elem = len(self.elems)
+        regs_T = n_elem + len(self.E_T) * len(self.F_T) + self.n_eriq
+        if n_elem <= 120 and self.n_eriq <= 64 and regs_T <= 240:
+            return "T"
+        return "W"
+
+    # ---- algorithmic flop count -------------------------------------------
+    def flops(self):
+        """(per primitive quartet, per contracted quartet) algorithmic FLOPs:
+        FMA = 2, add/mul = 1, div/sqrt/exp = 1; the VRR closure, Boys (table
+        Taylor + recursion), setup and accumulation per primitive quartet; the
+        recursive HGP HRR and the quantiser per quartet."""
+        vrr = 0
+        for (e, f, m), (kind, i) in self.elems.items():
+            if kind == "base":
+                vrr += 1
+            elif kind == "bra":
+                ep = vsub(e, UNIT[i])
+                vrr += 3 + (3 if ep[i] >= 1 else 0)
+            else:
+                fp = vsub(f, UNIT[i])
+                vrr += 3 + (3 if fp[i] >= 1 else 0) + (2 if e[i] >= 1 else 0)
+        setup = 30
+        boys = 30 + 3 * self.Ltot
+        acc = len(self.E_T) * len(self.F_T)
+        per_pq = setup + boys + vrr + acc
+        # recursive HRR: bra (a, b+1) = (a+1, b) + AB (a, b) over all f, then ket
+        a, b, c, d = self.a, self.b, self.c, self.d
+        hb = 0
+        for lb_ in range(1, b + 1):
+            hb += ncart(lb_) * sum(ncart(x) for x in range(a, a + b - lb_ + 1))
+        hb *= len(self.F_T)
+        hk = 0
+        for ld_ in range(1, d + 1):
+            hk += ncart(ld_) * sum(ncart(x) for x in range(c, c + d - ld_ + 1))
+        hk *= ncart(a) * ncart(b)
+        per_q = 2 * (hb + hk) + 3 * self.n_eriq
+        return per_pq, per_q
+
+
+# ---------------------------------------------------------------------------
+# Small code-emission helpers
+# ---------------------------------------------------------------------------
+class Emitter:
+    def __init__(self):
+        self.lines = []
+        self.ind = 0
+
+    def __call__(self, s=""):
+        self.lines.append("    " * self.ind + s)
+
+    def block(self, head):
+        self(head + " {")
+        self.ind += 1
+
+    def end(self, tail=""):
+        self.ind -= 1
+        self("}" + tail)
+
+    def text(self):
+        return "\n".join(self.lines) + "\n"
+
+
+def lit(x):
+    return repr(float(x))
+
+
+def binom(n, k):
+    return math.comb(n, k)
+
+
+def hrr_terms(b):
+    """(k, coef, powers) of (a, b| = sum_k C(b,k) (AB)^(b-k) (a+k, 0|."""
+    out = []
+    for kx in range(b[0] + 1):
+        for ky in range(b[1] + 1):
+            for kz in range(b[2] + 1):
+                coef = binom(b[0], kx) * binom(b[1], ky) * binom(b[2], kz)
+                out.append(((kx, ky, kz), coef, (b[0] - kx, b[1] - ky, b[2] - kz)))
+    return out
+
+
+def mono_name(prefix, pw):
+    if pw == ZERO:
+        return None
+    return "%s_%d%d%d" % (prefix, pw[0], pw[1], pw[2])
+
+
+def emit_hrr_coefs(em, prefix, base, bs, real):
+    """Declare the HRR coefficients C(b,k) (base)^(b-k) needed by the shells'
+    components `bs`, each as one named constant, so every use of a
+    coefficient reads the same bits."""
+    need = set()
+    for bb in bs:
+        for (_, coef, pw) in hrr_terms(bb):
+            if pw != ZERO:
+                need.add((coef, pw))
+    axis_max = [max([pw[i] for (_, pw) in need] + [0]) for i in range(3)]
+    for i, ax in enumerate("xyz"):
+        for k in range(1, axis_max[i] + 1):
+            if k == 1:
+                em("const %s %s_%s1 = (%s)%s[%d];" % (real, prefix, ax, real, base, i))
+            else:
+                em("const %s %s_%s%d = %s_%s%d * %s_%s1;" % (real, prefix, ax, k, prefix, ax, k - 1, prefix, ax))
+    for coef, pw in sorted(need):
+        parts = ["%s_%s%d" % (prefix, "xyz"[i], pw[i]) for i in range(3) if pw[i] > 0]
+        if coef != 1:
+            parts = ["(%s)%s" % (real, lit(coef))] + parts
+        em("const %s %s = %s;" % (real, coef_name(prefix, coef, pw), " * ".join(parts)))
+
+
+def coef_name(prefix, coef, pw):
+    return "%s_k%d_%d%d%d" % (prefix, coef, pw[0], pw[1], pw[2])
+
+
+def hrr_expr(b, a, getter, prefix):
+    """Closed-form HRR of (a, b| = sum_k C(b,k) (AB)^(b-k) (a+k, 0| from values
+    getter(a + k), as an explicit fma chain (evaluation order fixed)."""
+    terms = hrr_terms(b)
+    expr = None
+    for k, coef, pw in terms:
+        if pw == ZERO:
+            expr = getter(vadd(a, k))
+    for k, coef, pw in terms:
+        if pw == ZERO:
+            continue
+        expr = "fma(%s, %s, %s)" % (coef_name(prefix, coef, pw), getter(vadd(a, k)), expr)
+    return expr
+
+
+# ---------------------------------------------------------------------------
+# Mode T kernel
+# ---------------------------------------------------------------------------
+def emit_mode_T(cp, prec):
+    real = REALS[prec]
+    mixed = prec == "mixed"
+    em = Emitter()
+    name = "eri_%s_c%03d" % (prec, cp.cid)
+    a, b, c, d = cp.a, cp.b, cp.c, cp.d
+    em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode T, %s" % (cp.user + (cp.perm, a, b, c, d, prec)))
+    em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
+    em.block("")
+    em("const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;")
+    em("if (t >= A.n_items) return;")
+    em("const eri_item it = A.items[t];")
+    em("const eri_shell_pair BP = A.pairs[it.bra];")
+    em("const eri_shell_pair KP = A.pairs[it.ket];")
+    # accumulators
+    acc = {}
+    for e in cp.E_T:
+        for f in cp.F_T:
+            acc[(e, f)] = "acc_%d_%d_%d__%d_%d_%d" % (e + f)
+            em("double %s = 0.0;" % acc[(e, f)])
+    em.block("for (int ib = 0; ib < BP.nprim; ++ib)")
+    em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
+    em.block("for (int ik = 0; ik < KP.nprim; ++ik)")
+    em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
+    em("eri_pq_fp64 S;")
+    em("eri_pq_setup(B, K, S);")
+    em("double F[%d];" % (cp.Ltot + 1))
+    em("eri_boys<%d>(S.T, F);" % cp.Ltot)
+    # coefficients in the working type
+    em("const %s PAx = (%s)B.PA[0], PAy = (%s)B.PA[1], PAz = (%s)B.PA[2];" % ((real,) * 4))
+    em("const %s QCx = (%s)K.PA[0], QCy = (%s)K.PA[1], QCz = (%s)K.PA[2];" % ((real,) * 4))
+    em("const %s WPx = (%s)S.WP[0], WPy = (%s)S.WP[1], WPz = (%s)S.WP[2];" % ((real,) * 4))
+    em("const %s WQx = (%s)S.WQ[0], WQy = (%s)S.WQ[1], WQz = (%s)S.WQ[2];" % ((real,) * 4))
+    em("const %s hp = (%s)B.hp, hq = (%s)K.hp, hpq = (%s)S.hpq, rp = (%s)S.rho_p, rq = (%s)S.rho_q;" % ((real,) * 6))
+    names = {}
+    order = sorted(cp.elems.keys(), key=lambda el: (sum(el[1]), sum(el[0]), el[0], el[1], -el[2]))
+    n = 0
+    for el in order:
+        names[el] = "v%d" % n
+        n += 1
+    for el in order:
+        e, f, m = el
+        kind, i = cp.elems[el]
+        ax = "xyz"[i] if i is not None else None
+        if kind == "base":
+            expr = "(%s)(S.pref * F[%d])" % (real, m)
+        elif kind == "bra":
+            ep = vsub(e, UNIT[i])
+            expr = "PA%s * %s + WP%s * %s" % (ax, names[(ep, ZERO, m)], ax, names[(ep, ZERO, m + 1)])
+            if ep[i] >= 1:
+                epp = vsub(ep, UNIT[i])
+                expr += " + (%s * hp) * (%s - rp * %s)" % (lit(ep[i]), names[(epp, ZERO, m)], names[(epp, ZERO, m + 1)])
+        else:
+            fp = vsub(f, UNIT[i])
+            expr = "QC%s * %s + WQ%s * %s" % (ax, names[(e, fp, m)], ax, names[(e, fp, m + 1)])
+            if fp[i] >= 1:
+                fpp = vsub(fp, UNIT[i])
+                expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), names[(e, fpp, m)], names[(e, fpp, m + 1)])
+            if e[i] >= 1:
+                expr += " + (%s * hpq) * %s" % (lit(e[i]), names[(vsub(e, UNIT[i]), fp, m + 1)])
+        em("const %s %s = %s;" % (real, names[el], expr))
+    for e in cp.E_T:
+        for f in cp.F_T:
+            if mixed:
+                em("%s += (double)%s;" % (acc[(e, f)], names[(e, f, 0)]))
+            else:
+                em("%s += %s;" % (acc[(e, f)], names[(e, f, 0)]))
+    em.end()
+    em.end()
+    # HRR: ket first over every target e, then bra
+    ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
+    emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
+    emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
+    y = {}
+    for e in cp.E_T:
+        for ci in cc:
+            for di in cd:
+                nm = "y_%d%d%d_%d%d%d_%d%d%d" % (e + ci + di)
+                y[(e, ci, di)] = nm
+                expr = hrr_expr(di, ci, lambda f, e=e: "(%s)%s" % (real, acc[(e, f)]), "cd")
+                em("const %s %s = %s;" % (real, nm, expr))
+    outs = []
+    for ia, ai in enumerate(ca):
+        for ib_, bi in enumerate(cb):
+            for ic, ci in enumerate(cc):
+                for id_, di in enumerate(cd):
+                    nm = "o%d" % len(outs)
+                    expr = hrr_expr(bi, ai, lambda e, ci=ci, di=di: y[(e, ci, di)], "ab")
+                    em("const double %s = (double)(%s);" % (nm, expr))
+                    outs.append((nm, user_index(cp, ia, ib_, ic, id_)))
+    emit_store_T(em, cp, outs)
+    em.end()
+    return name, em.text()
+
+
+def user_strides(cp):
+    """Row-major strides of the user (a, b, c, d) layout, per computed shell."""
+    n = [ncart(L) for L in cp.user]
+    st = [n[1] * n[2] * n[3], n[2] * n[3], n[3], 1]
+    return [st[k] for k in cp.perm]
+
+
+def user_index(cp, ia, ib, ic, id_):
+    """Row-major (a,b,c,d) index in the user orientation of computed indices."""
+    st = user_strides(cp)
+    return ia * st[0] + ib * st[1] + ic * st[2] + id_ * st[3]
+
+
+def emit_store_T(em, cp, outs):
+    n = cp.n_eriq
+    em("const int64_t obase = t * %d;" % n)
+    em.block("if (A.out_eri)")
+    for nm, ui in outs:
+        em("A.out_eri[obase + %d] = %s;" % (ui, nm))
+    em.end()
+    em("double bmax = 0.0;")
+    for nm, _ in outs:
+        em("bmax = fmax(bmax, fabs(%s));" % nm)
+    em.block("if (A.out_codes)")
+    em("const double eps = bmax * A.cn;")
+    em("const double inv = eps > 0.0 ? 1.0 / eps : 0.0;")
+    em("if (A.out_scales) A.out_scales[t] = eps;")
+    for nm, ui in outs:
+        em("eri_store_code(A.out_codes, obase + %d, A.code_bytes, eri_quantize(%s, inv, A.qmax));" % (ui, nm))
+    em.end()
+
+
+# ---------------------------------------------------------------------------
+# Mode W kernel
+# ---------------------------------------------------------------------------
+def wave_layout(cp):
+    """Lanes per slot, subslot lists of bra indices e."""
+    all_e = [e for L in range(cp.Lab + 1) for e in comps(L)]
+    if len(all_e) <= 64:
+        subs = [all_e]
+    else:
+        subs = [[e for e in all_e if sum(e) % 2 == 0], [e for e in all_e if sum(e) % 2 == 1]]
+    ep = max(len(s) for s in subs)
+    return subs, ep
+
+
+def emit_mode_W(cp, prec, lds_budget=32768):
+    real = REALS[prec]
+    mixed = prec == "mixed"
+    em = Emitter()
+    name = "eri_%s_c%03d" % (prec, cp.cid)
+    a, b, c, d = cp.a, cp.b, cp.c, cp.d
+    subs, EP = wave_layout(cp)
+    S = len(subs)
+    NSLOT = 64 // EP
+    E_T = cp.E_T
+    tgt_index = {e: k for k, e in enumerate(E_T)}
+    NTE = len(E_T)
+    ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
+    NCD = len(cc) * len(cd)
+    NAB = len(ca) * len(cb)
+    CH = min(NCD, max(1, lds_budget // (8 * NSLOT * NTE)))
+    NCH = (NCD + CH - 1) // CH
+    src_sub = [0] if S == 1 else [1, 0]
+    # per-lane table: for each subslot: ex, ey, ez, valid, tgt, src_x, src_y, src_z
+    rows = []
+    for ls in range(EP):
+        row = []
+        for s in range(S):
+            if ls < len(subs[s]):
+                e = subs[s][ls]
+                src = []
+                for i in range(3):
+                    if e[i] >= 1:
+                        src.append(subs[src_sub[s]].index(vsub(e, UNIT[i])))
+                    else:
+                        src.append(ls)
+                row += [e[0], e[1], e[2], 1, tgt_index.get(e, -1)] + src
+            else:
+                row += [0, 0, 0, 0, -1, ls, ls, ls]
+        rows.append(row)
+    tbl = "eri_tbl_%s_c%03d" % (prec, cp.cid)
+    em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode W: %d lanes/slot, %d slot(s), %d subslot(s), %s"
+       % (cp.user + (cp.perm, a, b, c, d, EP, NSLOT, S, prec)))
+    em("static __constant__ signed char %s[%d][%d] = {" % (tbl, EP, 8 * S))
+    for row in rows:
+        em("  {" + ", ".join(str(v) for v in row) + "},")
+    em("};")
+    em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
+    em.block("")
+    em("__shared__ double s_t[%d][%d][%d];" % (NSLOT, NTE, CH))
+    em("__shared__ double s_red[64];")
+    em("const int lane = threadIdx.x;")
+    em("const int slot = lane / %d;" % EP)
+    em("const int ls = lane - slot * %d;" % EP)
+    em("const int64_t qi = (int64_t)blockIdx.x * %d + slot;" % NSLOT)
+    em("const bool active = slot < %d && qi < A.n_items;" % NSLOT)
+    em("const eri_item it = A.items[active ? qi : 0];")
+    em("const eri_shell_pair BP = A.pairs[it.bra];")
+    em("const eri_shell_pair KP = A.pairs[it.ket];")
+    em("const int nbra = active ? BP.nprim : 0;")
+    em("const int nket = KP.nprim;")
+    em("const int sbase = slot * %d;" % EP)
+    for s in range(S):
+        em("const int ex%d = %s[ls][%d], ey%d = %s[ls][%d], ez%d = %s[ls][%d];"
+           % (s, tbl, 8 * s, s, tbl, 8 * s + 1, s, tbl, 8 * s + 2))
+        em("const int tg%d = %s[ls][%d];" % (s, tbl, 8 * s + 4))
+        em("const int sx%d = sbase + %s[ls][%d], sy%d = sbase + %s[ls][%d], sz%d = sbase + %s[ls][%d];"
+           % (s, tbl, 8 * s + 5, s, tbl, 8 * s + 6, s, tbl, 8 * s + 7))
+    # accumulators per subslot
+    acc = {}
+    for s in range(S):
+        for f in cp.F_T:
+            acc[(s, f)] = "acc%d_%d%d%d" % ((s,) + f)
+            em("double %s = 0.0;" % acc[(s, f)])
+    em.block("for (int ib = 0; ib < nbra; ++ib)")
+    em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
+    em.block("for (int ik = 0; ik < nket; ++ik)")
+    em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
+    em("eri_pq_fp64 S;")
+    em("eri_pq_setup(B, K, S);")
+    em("double F[%d];" % (cp.Ltot + 1))
+    em("eri_boys<%d>(S.T, F);" % cp.Ltot)
+    em("const %s QCx = (%s)K.PA[0], QCy = (%s)K.PA[1], QCz = (%s)K.PA[2];" % ((real,) * 4))
+    em("const %s WQx = (%s)S.WQ[0], WQy = (%s)S.WQ[1], WQz = (%s)S.WQ[2];" % ((real,) * 4))
+    em("const %s hp = (%s)B.hp, hq = (%s)K.hp, hpq = (%s)S.hpq, rp = (%s)S.rho_p, rq = (%s)S.rho_q;" % ((real,) * 6))
+    MB = cp.Ltot
+    for s in range(S):
+        em("%s c%d[%d], p%d[%d], nx%d[%d];" % (real, s, MB + 2, s, MB + 2, s, MB + 2))
+        em("#pragma unroll")
+        em("for (int m = 0; m <= %d; ++m) { c%d[m] = (%s)(S.pref * F[m]); p%d[m] = (%s)0; }" % (MB, s, real, s, real))
+        em("const %s cex%d = (%s)ex%d * hpq, cey%d = (%s)ey%d * hpq, cez%d = (%s)ez%d * hpq;"
+           % (real, s, real, s, s, real, s, s, real, s))
+    # bra path: step t builds level t along z, then y, then x; lanes already
+    # at their |e| apply the identity (pa = 1, wp = 0, c = 0).
+    for s in range(S):
+        for t in range(1, cp.Lab + 1):
+            M = cp.Lcd + cp.Lab - t
+            em.block("")
+            em("const bool iz = %d <= ez%d;" % (t, s))
+            em("const bool iy = !iz && %d <= ez%d + ey%d;" % (t, s, s))
+            em("const bool ix = !iz && !iy && %d <= ez%d + ey%d + ex%d;" % (t, s, s, s))
+            em("const int nt = iz ? %d : iy ? %d - ez%d : ix ? %d - ez%d - ey%d : 0;" % (t - 1, t - 1, s, t - 1, s, s))
+            em("const %s pa = iz ? (%s)B.PA[2] : iy ? (%s)B.PA[1] : ix ? (%s)B.PA[0] : (%s)1;" % ((real,) * 5))
+            em("const %s wp = iz ? (%s)S.WP[2] : iy ? (%s)S.WP[1] : ix ? (%s)S.WP[0] : (%s)0;" % ((real,) * 5))
+            em("const %s cc = (%s)nt * hp;" % (real, real))
+            em("#pragma unroll")
+            em("for (int m = 0; m <= %d; ++m) nx%d[m] = pa * c%d[m] + wp * c%d[m + 1] + cc * (p%d[m] - rp * p%d[m + 1]);"
+               % (M, s, s, s, s, s))
+            em("#pragma unroll")
+            em("for (int m = 0; m <= %d; ++m) { p%d[m] = c%d[m]; c%d[m] = nx%d[m]; }" % (M, s, s, s, s))
+            em.end()
+    # ket VRR: values V_s(f, m), m <= Lcd - |f|
+    V = {}
+    kets = [f for L in range(cp.Lcd + 1) for f in comps(L)]
+    for s in range(S):
+        for m in range(cp.Lcd + 1):
+            V[(s, ZERO, m)] = "c%d[%d]" % (s, m)
+    nvar = 0
+    for f in kets:
+        if f == ZERO:
+            continue
+        L = sum(f)
+        i = lower_dir(f, cp.rule)
+        ax = "xyz"[i]
+        fp = vsub(f, UNIT[i])
+        for m in range(cp.Lcd - L + 1):
+            for s in range(S):
+                nm = "w%d" % nvar
+                nvar += 1
+                ss = src_sub[s]
+                expr = "QC%s * %s + WQ%s * %s" % (ax, V[(s, fp, m)], ax, V[(s, fp, m + 1)])
+                if fp[i] >= 1:
+                    fpp = vsub(fp, UNIT[i])
+                    expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), V[(s, fpp, m)], V[(s, fpp, m + 1)])
+                expr += " + ce%s%d * __shfl(%s, s%s%d)" % (ax, s, V[(ss, fp, m + 1)], ax, s)
+                em("const %s %s = %s;" % (real, nm, expr))
+                V[(s, f, m)] = nm
+    for s in range(S):
+        for f in cp.F_T:
+            v = V[(s, f, 0)]
+            em("%s += %s;" % (acc[(s, f)], ("(double)" + v) if mixed else v))
+    em.end()
+    em.end()
+    # HRR
+    em("const int64_t obase = qi * %d;" % cp.n_eriq)
+    emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
+    emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
+    cd_list = [(ci, di) for ci in cc for di in cd]
+    ab_list = [(ai, bi) for ai in ca for bi in cb]
+
+    def ket_hrr_chunk(ch):
+        lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
+        em("__syncthreads();")
+        for s in range(S):
+            em.block("if (active && tg%d >= 0)" % s)
+            for k in range(lo, hi):
+                ci, di = cd_list[k]
+                expr = hrr_expr(di, ci, lambda f, s=s: "(%s)%s" % (real, acc[(s, f)]), "cd")
+                em("s_t[slot][tg%d][%d] = (double)(%s);" % (s, k - lo, expr))
+            em.end()
+        em("__syncthreads();")
+
+    def bra_hrr_chunk(ch, pass_no):
+        lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
+        n = hi - lo
+        em.block("for (int j = ls; j < %d; j += %d)" % (n, EP))
+        em.block("if (active)")
+        em("const int kcd = %d + j;" % lo)
+        for k, (ai, bi) in enumerate(ab_list):
+            expr = hrr_expr(bi, ai, lambda e: "(%s)s_t[slot][%d][j]" % (real, tgt_index[e]), "ab")
+            em("const double x%d = (double)(%s);" % (k, expr))
+        # user-order index of (ab, kcd): computed (ic, id) = divmod(kcd, nd)
+        st = user_strides(cp)
+        nd = len(cd)
+        if st[2] == nd * st[3] and st[3] == 1:
+            em("const int64_t kx = kcd;")
+        else:
+            em("const int64_t kx = (int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d;" % (nd, st[2], nd, st[3]))
+        ab_off = [(ia_ * st[0] + ib_ * st[1]) for ia_ in range(len(ca)) for ib_ in range(len(cb))]
+        idx = "%d + kx"
+        for k in range(len(ab_list)):
+            ix = idx % ab_off[k]
+            if pass_no == 1:
+                em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                em("bmax = fmax(bmax, fabs(x%d));" % k)
+            else:
+                em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, inv, A.qmax));" % (ix, k))
+        em.end()
+        em.end()
+
+    em("double bmax = 0.0;")
+    for ch in range(NCH):
+        ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 1)
+    em("__syncthreads();")
+    em("s_red[lane] = bmax;")
+    em("__syncthreads();")
+    em.block("if (A.out_codes)")
+    em("double m = 0.0;")
+    em("if (slot < %d) for (int k = 0; k < %d; ++k) m = fmax(m, s_red[sbase + k]);" % (NSLOT, EP))
+    em("const double eps = m * A.cn;")
+    em("const double inv = eps > 0.0 ? 1.0 / eps : 0.0;")
+    em("if (active && ls == 0 && A.out_scales) A.out_scales[qi] = eps;")
+    for ch in range(NCH):
+        ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 2)
+    em.end()
+    em.end()
+    return name, em.text()
+
+
+def emit_class(cp, prec):
+    if cp.mode == "T":
+        return emit_mode_T(cp, prec)
+    return emit_mode_W(cp, prec)
+
+
+HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
+#include "eri_device.h"
+"""
+
+
+def kernel_info_init(cp, name):
+    subs, EP = wave_layout(cp)
+    per_pq, per_q = cp.flops()
+    pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
+    if cp.mode == "T":
+        return "{(const void*)%s, 0, 64, 64, %d, %d, %d, %d, 0}" % (name, cp.n_eriq, per_pq, per_q, pk)
+    return "{(const void*)%s, 1, 64, %d, %d, %d, %d, %d, 0}" % (name, 64 // EP, cp.n_eriq, per_pq, per_q, pk)
+
+
+def generate(outdir, precisions=("fp64",), classes=range(256), group=8, overrides=None):
+    """Write kernel sources (grouped `group` classes per file, each with a host
+    registration function filling its entries of the kernel table) and the
+    table TU; returns (list of source files, dict of ClassPlan)."""
+    os.makedirs(outdir, exist_ok=True)
+    overrides = overrides or {}
+    plans = {}
+    files = []
+    regs = []
+    classes = list(classes)
+    for g in range(0, len(classes), group):
+        chunk = classes[g:g + group]
+        for prec in precisions:
+            parts = [HEADER, '#include "eri_dispatch.h"']
+            reg = []
+            for cid in chunk:
+                la, lb, lc, ld = class_of(cid)
+                cp = plans.get(cid)
+                if cp is None:
+                    kw = overrides.get(cid, {})
+                    cp = ClassPlan(la, lb, lc, ld, **kw)
+                    plans[cid] = cp
+                name, src = emit_class(cp, prec)
+                parts.append(src)
+                reg.append("    t[%d] = %s;" % (cid, kernel_info_init(cp, name)))
+            fname = "eri_register_%s_g%03d" % (prec, g // group)
+            parts.append("void %s(eri_kernel_info* t)\n{\n%s\n}\n" % (fname, "\n".join(reg)))
+            regs.append((prec, fname))
+            fn = os.path.join(outdir, "eri_%s_g%03d.hip" % (prec, g // group))
+            write_if_changed(fn, "\n".join(parts))
+            files.append(fn)
+    lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
+    for prec, fname in regs:
+        lines.append("void %s(eri_kernel_info* t);" % fname)
+    lines.append("static eri_kernel_info g_fp64[256], g_mixed[256];")
+    lines.append("static std::once_flag g_once;")
+    lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
+    lines.append("{")
+    lines.append("    std::call_once(g_once, [] {")
+    for prec, fname in regs:
+        lines.append("        %s(%s);" % (fname, "g_fp64" if prec == "fp64" else "g_mixed"))
+    lines.append("    });")
+    lines.append("    return precision == 1 ? g_mixed : g_fp64;")
+    lines.append("}")
+    fn = os.path.join(outdir, "eri_dispatch_table.hip")
+    write_if_changed(fn, "\n".join(lines) + "\n")
+    files.append(fn)
+    return files, plans
+
+
+def write_if_changed(fn, text):
+    if os.path.exists(fn):
+        with open(fn) as f:
+            if f.read() == text:
+                return
+    with open(fn, "w") as f:
+        f.write(text)

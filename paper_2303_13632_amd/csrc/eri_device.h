@@ -1,0 +1,102 @@
+// Device-side building blocks shared by every generated class kernel:
+// plan record layouts, the Boys function, the per-primitive-quartet setup of
+// the Obara-Saika recurrences, and the fused n-bit quantiser.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "eri_plan_types.h"
+#include "boys_table.h"
+
+#define ERI_DEV __device__ __forceinline__
+
+// 2 pi^(5/2)
+#define ERI_TWO_PI_52 34.98683665524972497
+
+// ---------------------------------------------------------------------------
+// Boys function F_m(T), m = 0..MMAX (MMAX a compile-time constant).
+// T < ERI_BOYS_TMAX: Taylor expansion of F_MMAX about the nearest grid point
+//   T_k = k * ERI_BOYS_DT of a table of exact values (d/dT F_m = -F_{m+1}),
+//   nine terms, then the downward relation F_m = (2T F_{m+1} + e^-T)/(2m+1).
+// T >= ERI_BOYS_TMAX: F_0 = sqrt(pi/T)/2 (erfc(sqrt T) < 3e-17 there) and the
+//   upward relation F_{m+1} = ((2m+1) F_m - e^-T)/(2T), stable for T > m.
+// ---------------------------------------------------------------------------
+template <int MMAX>
+ERI_DEV void eri_boys(double T, double* __restrict__ F)
+{
+    const double et = exp(-T);
+    if (T < ERI_BOYS_TMAX) {
+        const int k = __double2int_rn(T * (1.0 / ERI_BOYS_DT));
+        const double d = (double)k * ERI_BOYS_DT - T;
+        const double* __restrict__ row = eri_boys_table + k * ERI_BOYS_NCOL + MMAX;
+        double s = row[8];
+        s = fma(s, d * (1.0 / 8.0), row[7]);
+        s = fma(s, d * (1.0 / 7.0), row[6]);
+        s = fma(s, d * (1.0 / 6.0), row[5]);
+        s = fma(s, d * (1.0 / 5.0), row[4]);
+        s = fma(s, d * (1.0 / 4.0), row[3]);
+        s = fma(s, d * (1.0 / 3.0), row[2]);
+        s = fma(s, d * (1.0 / 2.0), row[1]);
+        s = fma(s, d, row[0]);
+        F[MMAX] = s;
+#pragma unroll
+        for (int m = MMAX - 1; m >= 0; --m)
+            F[m] = fma(2.0 * T, F[m + 1], et) * (1.0 / (double)(2 * m + 1));
+    } else {
+        const double it = 1.0 / T;
+        F[0] = 0.88622692545275801365 * sqrt(it);  // sqrt(pi)/2 / sqrt(T)
+        const double h = 0.5 * it;
+#pragma unroll
+        for (int m = 0; m < MMAX; ++m)
+            F[m + 1] = fma((double)(2 * m + 1), F[m], -et) * h;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per primitive quartet quantities of the Obara-Saika scheme.
+// ---------------------------------------------------------------------------
+struct eri_pq_fp64 {
+    double T, pref;          // Boys argument and 2 pi^(5/2) K_ab K_cd / (p q sqrt(p+q))
+    double WP[3], WQ[3];     // W - P, W - Q
+    double rho_p, rho_q;     // rho/p, rho/q
+    double hpq;              // 1/(2(p+q))
+};
+
+ERI_DEV void eri_pq_setup(const eri_prim_pair& B, const eri_prim_pair& K, eri_pq_fp64& s)
+{
+    const double pq = B.p + K.p;
+    const double ipq = 1.0 / pq;
+    const double PQx = B.P[0] - K.P[0], PQy = B.P[1] - K.P[1], PQz = B.P[2] - K.P[2];
+    const double rho = B.p * K.p * ipq;
+    s.T = rho * (PQx * PQx + PQy * PQy + PQz * PQz);
+    s.pref = ERI_TWO_PI_52 * B.kp * K.kp * sqrt(ipq);
+    const double fq = -K.p * ipq, fp = B.p * ipq;
+    s.WP[0] = fq * PQx; s.WP[1] = fq * PQy; s.WP[2] = fq * PQz;
+    s.WQ[0] = fp * PQx; s.WQ[1] = fp * PQy; s.WQ[2] = fp * PQz;
+    s.rho_p = K.p * ipq;
+    s.rho_q = B.p * ipq;
+    s.hpq = 0.5 * ipq;
+}
+
+// ---------------------------------------------------------------------------
+// Quantiser of the fused compression: eps = b_max * c_n, inv = 1/eps,
+// q = round-half-away(x * inv) clamped to +-qmax; eps == 0 gives q = 0.
+// Each product is a single IEEE rounding (no add follows, so nothing fuses).
+// ---------------------------------------------------------------------------
+ERI_DEV int eri_quantize(double x, double inv, double qmax)
+{
+    double y = round(x * inv);
+    y = y > qmax ? qmax : y;
+    y = y < -qmax ? -qmax : y;
+    return (int)y;
+}
+
+ERI_DEV void eri_store_code(void* codes, int64_t idx, int bytes, int q)
+{
+    if (bytes == 2)
+        reinterpret_cast<int16_t*>(codes)[idx] = (int16_t)q;
+    else if (bytes == 1)
+        reinterpret_cast<int8_t*>(codes)[idx] = (int8_t)q;
+    else
+        reinterpret_cast<int32_t*>(codes)[idx] = q;
+}

@@ -1,0 +1,19 @@
+// Table of the generated class kernels.
+#pragma once
+#include <stdint.h>
+
+struct eri_kernel_info {
+    const void* fn;      // __global__ entry, one eri_class_args argument
+    int32_t mode;        // 0: one lane per quartet; 1: one slot of lanes per quartet
+    int32_t block;       // threads per workgroup
+    int32_t per_block;   // quartets per workgroup
+    int32_t n_eriq;      // ERIs per quartet
+    int32_t flops_pq;    // algorithmic FLOPs per primitive quartet
+    int32_t flops_q;     // algorithmic FLOPs per contracted quartet (HRR + quantiser)
+    int32_t perm;        // computed shell k is user shell (perm >> 2k) & 3
+    int32_t pad;
+};
+
+// Kernel table of a precision (0: FP64, 1: FP32-mixed); entries of classes
+// without a kernel have fn == nullptr.
+const eri_kernel_info* eri_kernel_table(int precision);

@@ -1,0 +1,235 @@
+"""Python binding of liberi_hip.so (include/eri.h): argument marshalling only.
+
+Every step of the ERI computation and compression runs in the library's HIP
+kernels; PyTorch supplies device memory and streams.  If the library has not
+been built, loading fails with an error (there is no fallback path).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liberi_hip.so")
+HEADER = os.path.join(os.path.dirname(_PKG), "include", "eri.h")
+
+ERI_OK = 0
+ERI_EINVAL = -1
+ERI_EUNSUPPORTED = -2
+ERI_ENOMEM = -3
+ERI_EHIP = -4
+ERI_ESTATE = -5
+ERI_FP64 = 0
+ERI_FP32_MIXED = 1
+PRECISIONS = {"fp64": ERI_FP64, "mixed": ERI_FP32_MIXED}
+
+_lib = None
+
+
+class EriError(RuntimeError):
+    def __init__(self, status, where):
+        lib = load()
+        msg = lib.eri_status_string(status).decode()
+        if status == ERI_EHIP:
+            msg += " (hipError %d)" % lib.eri_last_hip_error()
+        super().__init__("%s: %s" % (where, msg))
+        self.status = status
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("bits", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_quartets", ctypes.c_int64), ("n_eri", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("n_prim_pairs", ctypes.c_int64),
+                ("n_prim_quartets", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("code_bytes", ctypes.c_int32), ("bits", ctypes.c_int32),
+                ("class_quartets", ctypes.c_int64 * 256), ("class_eri_off", ctypes.c_int64 * 257),
+                ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256)]
+
+
+_vp = ctypes.c_void_p
+_i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+
+
+def load():
+    """Load the HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liberi_hip.so is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.eri_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int64, _i32p, _i32p, _f64p, _i64p,
+                                    _f64p, _f64p, _i32p, ctypes.c_int64, ctypes.POINTER(PlanOpts)]
+    lib.eri_plan_info_get.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
+    lib.eri_plan_layout.argtypes = [_vp, _i64p, _i64p]
+    lib.eri_compute.argtypes = [_vp, _vp, _vp, _vp, _vp]
+    lib.eri_compute_class.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+    lib.eri_compress.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
+    lib.eri_decompress.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.eri_plan_destroy.argtypes = [_vp]
+    lib.eri_plan_destroy.restype = None
+    lib.eri_status_string.argtypes = [ctypes.c_int]
+    lib.eri_status_string.restype = ctypes.c_char_p
+    lib.eri_last_hip_error.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def declared_symbols():
+    """Function names declared in include/eri.h."""
+    import re
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(eri_\w+)\s*\(", txt, re.M)))
+
+
+def _check(rc, where):
+    if rc != ERI_OK:
+        raise EriError(rc, where)
+
+
+def code_dtype(bits):
+    import torch
+    if bits <= 0:
+        return None
+    return torch.int8 if bits <= 8 else torch.int16 if bits <= 16 else torch.int32
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A plan over the quartets of a shell set (see include/eri.h)."""
+
+    def __init__(self, shells, quartets, precision="fp64", bits=16, device=0):
+        lib = load()
+        self.shells = shells
+        q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+        self.quartets = q
+        self.precision = precision
+        self.bits = int(bits)
+        self.device = int(device)
+        opts = PlanOpts(PRECISIONS[precision], self.bits, self.device, 0)
+        h = _vp()
+        L = np.ascontiguousarray(shells["L"], dtype=np.int32)
+        K = np.ascontiguousarray(shells["K"], dtype=np.int32)
+        xyz = np.ascontiguousarray(shells["xyz"], dtype=np.float64).reshape(-1)
+        off = np.ascontiguousarray(shells["off"], dtype=np.int64)
+        ex = np.ascontiguousarray(shells["exps"], dtype=np.float64)
+        co = np.ascontiguousarray(shells["coefs"], dtype=np.float64)
+        if len(ex) == 0:
+            ex = np.zeros(1)
+            co = np.zeros(1)
+        rc = lib.eri_plan_create(ctypes.byref(h), len(L), L, K, xyz, off, ex, co,
+                                 q.reshape(-1) if len(q) else np.zeros(4, dtype=np.int32), len(q),
+                                 ctypes.byref(opts))
+        _check(rc, "eri_plan_create")
+        self._h = h
+        info = PlanInfo()
+        _check(lib.eri_plan_info_get(h, ctypes.byref(info)), "eri_plan_info_get")
+        self.n_quartets = info.n_quartets
+        self.n_eri = info.n_eri
+        self.n_prim_quartets = info.n_prim_quartets
+        self.n_pairs = info.n_pairs
+        self.n_prim_pairs = info.n_prim_pairs
+        self.device_bytes = info.device_bytes
+        self.code_bytes = info.code_bytes
+        self.class_quartets = np.array(info.class_quartets[:], dtype=np.int64)
+        self.class_eri_off = np.array(info.class_eri_off[:], dtype=np.int64)
+        self.class_quartet_off = np.array(info.class_quartet_off[:], dtype=np.int64)
+        self.class_flops = np.array(info.class_flops[:], dtype=np.float64)
+        self._pos = None
+        self._eri_off = None
+
+    def layout(self):
+        """(pos, eri_off) per user quartet (plan position, first ERI)."""
+        if self._pos is None:
+            n = int(self.n_quartets)
+            pos = np.zeros(max(n, 1), dtype=np.int64)
+            eoff = np.zeros(max(n, 1), dtype=np.int64)
+            _check(load().eri_plan_layout(self._h, pos, eoff), "eri_plan_layout")
+            self._pos, self._eri_off = pos[:n], eoff[:n]
+        return self._pos, self._eri_off
+
+    def alloc(self, eri=True, codes=True):
+        import torch
+        dev = torch.device("cuda", self.device)
+        out_eri = torch.empty(max(int(self.n_eri), 1), dtype=torch.float64, device=dev) if eri else None
+        out_codes = out_scales = None
+        if codes and self.bits > 0:
+            out_codes = torch.empty(max(int(self.n_eri), 1), dtype=code_dtype(self.bits), device=dev)
+            out_scales = torch.empty(max(int(self.n_quartets), 1), dtype=torch.float64, device=dev)
+        return out_eri, out_codes, out_scales
+
+    def compute(self, out_eri=None, out_codes=None, out_scales=None, stream=None):
+        _check(load().eri_compute(self._h, _stream(stream), _ptr(out_eri), _ptr(out_codes), _ptr(out_scales)),
+               "eri_compute")
+
+    def compute_class(self, cid, out_eri=None, out_codes=None, out_scales=None, stream=None):
+        _check(load().eri_compute_class(self._h, int(cid), _stream(stream), _ptr(out_eri), _ptr(out_codes),
+                                        _ptr(out_scales)), "eri_compute_class")
+
+    def to_user(self, values):
+        """Plan-order per-ERI array (numpy) -> user order (concatenated blocks)."""
+        pos, eoff = self.layout()
+        L = self.shells["L"]
+        sizes = np.array([_ncart(L[a]) * _ncart(L[b]) * _ncart(L[c]) * _ncart(L[d]) for a, b, c, d in self.quartets],
+                         dtype=np.int64)
+        idx = np.concatenate([np.arange(o, o + s) for o, s in zip(eoff, sizes)]) if len(sizes) else np.zeros(0, np.int64)
+        return values[idx]
+
+    def scales_to_user(self, scales):
+        pos, _ = self.layout()
+        return scales[pos]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().eri_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ncart(L):
+    return (int(L) + 1) * (int(L) + 2) // 2
+
+
+def compress(bits, eri, block_off, codes=None, scales=None, stream=None):
+    """eqs. 9-10 on device tensors: returns (codes, scales)."""
+    import torch
+    nb = block_off.numel() - 1
+    if codes is None:
+        codes = torch.empty(eri.numel(), dtype=code_dtype(bits), device=eri.device)
+    if scales is None:
+        scales = torch.empty(max(nb, 1), dtype=torch.float64, device=eri.device)
+    _check(load().eri_compress(int(bits), _ptr(eri), nb, _ptr(block_off), _ptr(codes), _ptr(scales),
+                               _stream(stream)), "eri_compress")
+    return codes, scales
+
+
+def decompress(bits, codes, scales, block_off, out=None, stream=None):
+    """eq. 11 on device tensors."""
+    import torch
+    nb = block_off.numel() - 1
+    if out is None:
+        out = torch.empty(codes.numel(), dtype=torch.float64, device=codes.device)
+    _check(load().eri_decompress(int(bits), _ptr(codes), _ptr(scales), nb, _ptr(block_off), _ptr(out),
+                                 _stream(stream)), "eri_decompress")
+    return out

@@ -1,0 +1,157 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: FP64 ERIs within 1e-12 Hartree absolute of the oracle (a 1e-14
+relative allowance covers quartets whose values reach O(100) Ha, where the
+oracle's own double rounding is of that order); the fused codes and scales
+bit-identical to the oracle's compressor fed the GPU's doubles; decompressed
+values within half a quantisation step."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2303_13632_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+N_PER_CLASS = 67          # ragged against 64-lane and multi-slot workgroups
+ABS_TOL = 1e-12
+REL_TOL = 1e-14
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _eri_gpu(shells, quartets, precision="fp64", bits=16):
+    from paper_2303_13632_amd import eri
+    plan = eri.Plan(shells, quartets, precision=precision, bits=bits)
+    out_eri, out_codes, out_scales = plan.alloc(eri=True, codes=bits > 0)
+    plan.compute(out_eri, out_codes, out_scales)
+    torch.cuda.synchronize()
+    vals = out_eri.cpu().numpy()[: plan.n_eri]
+    codes = out_codes.cpu().numpy()[: plan.n_eri].astype(np.int32) if bits > 0 else None
+    scales = out_scales.cpu().numpy()[: plan.n_quartets] if bits > 0 else None
+    return plan, vals, codes, scales
+
+
+def _blocks(sizes):
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off
+
+
+@pytest.fixture(scope="module")
+def all_classes():
+    parts = [W.class_case(cid, n_quartets=N_PER_CLASS) for cid in range(256)]
+    shells, quartets = W.merge(parts)
+    print("oracle: %d quartets" % len(quartets), flush=True)
+    ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
+    return shells, quartets, ref, sizes
+
+
+def test_all_classes_fp64_and_int16(all_classes):
+    shells, quartets, ref, sizes = all_classes
+    plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
+    got = plan.to_user(vals)
+    cls = np.repeat(np.arange(256), N_PER_CLASS)
+    qcls = np.repeat(cls, sizes)
+    err = np.abs(got - ref)
+    tol = ABS_TOL + REL_TOL * np.abs(ref)
+    worst = []
+    for c in range(256):
+        m = qcls == c
+        e = err[m].max()
+        worst.append((e, c))
+        if not np.all(err[m] <= tol[m]):
+            i = np.argmax(err[m] - tol[m])
+            pytest.fail("class %d %s: max err %.3e (value %.3e)" % (c, W.class_of(c), e, ref[m][i]))
+    worst.sort(reverse=True)
+    print("worst classes:", [(W.class_of(c), "%.2e" % e) for e, c in worst[:5]])
+    # fused compression: codes and scales bit-identical to the oracle's compressor
+    # applied to the GPU's own doubles, block = one quartet (plan order)
+    blk = _blocks(np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets))
+    oc, oe = O.compress(16, vals, blk)
+    assert np.array_equal(oe, scales)
+    bad = np.nonzero(oc != codes)[0]
+    if len(bad):
+        qbad = np.searchsorted(blk, bad[0], side="right") - 1
+        cbad = np.searchsorted(plan.class_quartet_off, qbad, side="right") - 1
+        pytest.fail("%d codes differ; first in class %d %s" % (len(bad), cbad, W.class_of(int(cbad))))
+    dec = O.decompress(codes, scales, blk)
+    for b in range(len(blk) - 1):
+        s = slice(blk[b], blk[b + 1])
+        assert np.max(np.abs(dec[s] - vals[s])) <= scales[b] / 2 + 4 * np.spacing(np.max(np.abs(vals[s])))
+
+
+@pytest.mark.parametrize("bits", [8, 12, 32])
+def test_fused_bit_widths(bits):
+    parts = [W.class_case(cid, n_quartets=40) for cid in (0, 21, 85, 106, 170, 231, 255)]
+    shells, quartets = W.merge(parts)
+    plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=bits)
+    sizes = np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets)
+    blk = _blocks(sizes)
+    oc, oe = O.compress(bits, vals, blk)
+    assert np.array_equal(oe, scales)
+    assert np.array_equal(oc, codes)
+
+
+def test_small_case_ss_ss_k3():
+    """(ss|ss), K = 3, 4096 quartets: every quartet against the oracle."""
+    shells, quartets = W.small_case()
+    ref, _, _ = O.eri(shells, quartets, n_threads=THREADS)
+    plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
+    got = plan.to_user(vals)
+    assert np.max(np.abs(got - ref)) <= ABS_TOL
+    # one value per quartet: each code is +-(2^15-1) or 0 at block = quartet
+    assert np.all(np.isin(np.abs(codes), [0, 32767]))
+
+
+def test_degenerate_geometries():
+    """All four centres equal (T = 0, parity zeros), very tight and very
+    diffuse exponents, far-apart pairs (large T)."""
+    rng = np.random.default_rng(99)
+    parts = []
+    for cid in (0, 5, 21, 64, 85, 150, 255, 27, 228):
+        sh, q = W.class_case(cid, n_quartets=12, seed=777)
+        sh["xyz"] = sh["xyz"].copy()
+        sh["exps"] = sh["exps"].copy()
+        n = len(sh["L"])
+        sh["xyz"][0:16] = sh["xyz"][0]             # quartets 0..3: one centre
+        sh["xyz"][16:24] = sh["xyz"][16] + np.array([0, 0, 40.0])  # far apart
+        sh["exps"][: len(sh["exps"]) // 3] *= 50.0   # tight
+        parts.append((sh, q))
+    shells, quartets = W.merge(parts)
+    ref, _, _ = O.eri(shells, quartets, n_threads=THREADS)
+    plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
+    got = plan.to_user(vals)
+    assert np.all(np.abs(got - ref) <= ABS_TOL + REL_TOL * np.abs(ref))
+
+
+def test_empty_plan():
+    from paper_2303_13632_amd import eri
+    sh, q = W.class_case(0, n_quartets=1)
+    plan = eri.Plan(sh, q[:0], bits=16)
+    assert plan.n_quartets == 0 and plan.n_eri == 0
+    e, c, s = plan.alloc()
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+
+
+def test_standalone_compress_decompress():
+    from paper_2303_13632_amd import eri
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(1, 400, size=300)
+    sizes[7] = 0
+    off = _blocks(sizes)
+    x = rng.standard_normal(off[-1]) * np.repeat(10.0 ** rng.uniform(-9, 2, size=300), sizes)
+    x[off[3]:off[4]] = 0.0
+    dx = torch.from_numpy(x).cuda()
+    doff = torch.from_numpy(off).cuda()
+    for bits in (4, 8, 12, 16, 24, 32):
+        codes, scales = eri.compress(bits, dx, doff)
+        out = eri.decompress(bits, codes, scales, doff)
+        torch.cuda.synchronize()
+        oc, oe = O.compress(bits, x, off)
+        assert np.array_equal(scales.cpu().numpy()[: len(sizes)], oe)
+        assert np.array_equal(codes.cpu().numpy().astype(np.int32), oc)
+        assert np.array_equal(out.cpu().numpy(), O.decompress(oc, oe, off))

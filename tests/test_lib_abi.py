@@ -1,0 +1,74 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/eri.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_2303_13632_amd import eri, workloads as W
+
+
+def test_library_exports_declared_symbols():
+    lib = eri.load()
+    names = eri.declared_symbols()
+    assert "eri_plan_create" in names and "eri_compute" in names and "eri_compress" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    lib = eri.load()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert len(lib.eri_status_string(code)) >= 2
+    assert lib.eri_status_string(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("L", 4, eri.ERI_EUNSUPPORTED),
+    ("L", -1, eri.ERI_EUNSUPPORTED),
+    ("K", 0, eri.ERI_EUNSUPPORTED),
+    ("K", 17, eri.ERI_EUNSUPPORTED),
+])
+def test_plan_rejects_bad_shells(field, value, status):
+    sh, q = W.random_class_quartets(1, 0, 0, 0, 3, seed=1, k_fixed=2)
+    sh[field] = sh[field].copy()
+    sh[field][1] = value
+    with pytest.raises(eri.EriError) as ei:
+        eri.Plan(sh, q)
+    assert ei.value.status == status
+
+
+def test_plan_rejects_bad_quartet_index_and_bits():
+    sh, q = W.random_class_quartets(0, 0, 0, 0, 3, seed=1, k_fixed=1)
+    bad = q.copy()
+    bad[1, 2] = len(sh["L"])
+    with pytest.raises(eri.EriError) as ei:
+        eri.Plan(sh, bad)
+    assert ei.value.status == eri.ERI_EINVAL
+    for bits in (1, 33, -2):
+        with pytest.raises(eri.EriError) as ei:
+            eri.Plan(sh, q, bits=bits)
+        assert ei.value.status == eri.ERI_EUNSUPPORTED
+
+
+def test_plan_rejects_nonpositive_exponent():
+    sh, q = W.random_class_quartets(0, 0, 0, 0, 2, seed=2, k_fixed=1)
+    sh["exps"] = sh["exps"].copy()
+    sh["exps"][0] = 0.0
+    with pytest.raises(eri.EriError) as ei:
+        eri.Plan(sh, q)
+    assert ei.value.status == eri.ERI_EINVAL
+
+
+def test_null_arguments():
+    lib = eri.load()
+    assert lib.eri_plan_info_get(None, None) == eri.ERI_EINVAL
+    assert lib.eri_compute(None, None, None, None, None) == eri.ERI_EINVAL
+    assert lib.eri_compress(1, None, 0, None, None, None, None) == eri.ERI_EUNSUPPORTED
+    assert lib.eri_compress(16, None, 3, None, None, None, None) == eri.ERI_EINVAL
+    assert lib.eri_decompress(40, None, None, 0, None, None, None) == eri.ERI_EUNSUPPORTED
+    assert lib.eri_compress(16, None, 0, None, None, None, None) == eri.ERI_OK
+    h = ctypes.c_void_p()
+    assert lib.eri_plan_create(ctypes.byref(h), -1, np.zeros(1, np.int32), np.zeros(1, np.int32),
+                               np.zeros(3), np.zeros(2, np.int64), np.zeros(1), np.zeros(1),
+                               np.zeros(4, np.int32), 0, ctypes.byref(eri.PlanOpts(0, 16, 0, 0))) == eri.ERI_EINVAL
