@@ -38,7 +38,8 @@
  *   - Contracted shells: sum_k c_k N(alpha_k, L) g(alpha_k), no renormalisation.
  *   - Compression: c_n = 1.0/(2^(n-1)-1); eps = b_max*c_n; inv = 1.0/eps (the
  *     single division of the paper's footnote); q = round-half-away(x*inv),
- *     clamped to +-(2^(n-1)-1); b_max = 0 gives eps = 0 and all codes 0.
+ *     clamped to +-(2^(n-1)-1); b_max = 0 gives eps = 0 and all codes 0; when
+ *     eps is so small (subnormal) that 1/eps overflows, q = ANINT(x/eps).
  *     Built with -ffp-contract=off so every operation is one IEEE rounding.
  *
  * Two instantiations of the quadrature core are built: one in double (roots
@@ -427,8 +428,9 @@ int oracle_compress(int bits, int64_t n_blocks, const int64_t *off, const double
             continue;
         }
         double inv = 1.0 / eps;
+        const int overflow = isinf(inv);           /* eps subnormal: divide instead */
         for (int64_t i = off[b]; i < off[b + 1]; ++i) {
-            double y = round(x[i] * inv);          /* ANINT: nearest, ties away from zero */
+            double y = round(overflow ? x[i] / eps : x[i] * inv);   /* ANINT: ties away from zero */
             if (y > qmax) y = qmax;
             if (y < -qmax) y = -qmax;
             codes[i] = (int32_t)y;

@@ -440,10 +440,10 @@ def emit_store_T(em, cp, outs):
         em("bmax = fmax(bmax, fabs(%s));" % nm)
     em.block("if (A.out_codes)")
     em("const double eps = bmax * A.cn;")
-    em("const double inv = eps > 0.0 ? 1.0 / eps : 0.0;")
+    em("const double inv = eri_inverse_scale(eps);")
     em("if (A.out_scales) A.out_scales[t] = eps;")
     for nm, ui in outs:
-        em("eri_store_code(A.out_codes, obase + %d, A.code_bytes, eri_quantize(%s, inv, A.qmax));" % (ui, nm))
+        em("eri_store_code(A.out_codes, obase + %d, A.code_bytes, eri_quantize(%s, eps, inv, A.qmax));" % (ui, nm))
     em.end()
 
 
@@ -642,7 +642,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
                 em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
             else:
-                em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, inv, A.qmax));" % (ix, k))
+                em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
         em.end()
         em.end()
 
@@ -657,7 +657,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     em("double m = 0.0;")
     em("if (slot < %d) for (int k = 0; k < %d; ++k) m = fmax(m, s_red[sbase + k]);" % (NSLOT, EP))
     em("const double eps = m * A.cn;")
-    em("const double inv = eps > 0.0 ? 1.0 / eps : 0.0;")
+    em("const double inv = eri_inverse_scale(eps);")
     em("if (active && ls == 0 && A.out_scales) A.out_scales[qi] = eps;")
     for ch in range(NCH):
         ket_hrr_chunk(ch)

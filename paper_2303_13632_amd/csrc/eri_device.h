@@ -80,12 +80,16 @@ ERI_DEV void eri_pq_setup(const eri_prim_pair& B, const eri_prim_pair& K, eri_pq
 
 // ---------------------------------------------------------------------------
 // Quantiser of the fused compression: eps = b_max * c_n, inv = 1/eps,
-// q = round-half-away(x * inv) clamped to +-qmax; eps == 0 gives q = 0.
+// q = round-half-away(x * inv) clamped to +-qmax; eps == 0 gives q = 0; a
+// subnormal eps whose reciprocal overflows is handled by dividing, x / eps.
 // Each product is a single IEEE rounding (no add follows, so nothing fuses).
 // ---------------------------------------------------------------------------
-ERI_DEV int eri_quantize(double x, double inv, double qmax)
+ERI_DEV double eri_inverse_scale(double eps) { return eps > 0.0 ? 1.0 / eps : 0.0; }
+
+ERI_DEV int eri_quantize(double x, double eps, double inv, double qmax)
 {
-    double y = round(x * inv);
+    if (eps == 0.0) return 0;
+    double y = round(__builtin_isinf(inv) ? x / eps : x * inv);
     y = y > qmax ? qmax : y;
     y = y < -qmax ? -qmax : y;
     return (int)y;

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "eri.h"
+#include "eri_device.h"
 #include "eri_dispatch.h"
 #include "eri_plan_types.h"
 
@@ -393,14 +394,9 @@ __global__ __launch_bounds__(64) void eri_compress_kernel(const double* __restri
     for (int64_t i = lo + threadIdx.x; i < hi; i += 64) m = fmax(m, fabs(x[i]));
     for (int s = 32; s > 0; s >>= 1) m = fmax(m, __shfl_xor(m, s));
     const double eps = m * cn;
-    const double inv = eps > 0.0 ? 1.0 / eps : 0.0;
+    const double inv = eri_inverse_scale(eps);
     if (threadIdx.x == 0) scales[b] = eps;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 64) {
-        double y = round(x[i] * inv);
-        y = y > qmax ? qmax : y;
-        y = y < -qmax ? -qmax : y;
-        codes[i] = (CT)(int)y;
-    }
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 64) codes[i] = (CT)eri_quantize(x[i], eps, inv, qmax);
 }
 
 template <typename CT>

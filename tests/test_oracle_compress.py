@@ -27,8 +27,9 @@ def numpy_compress(bits, x, off):
         eps[b] = e
         if e == 0.0:
             continue
-        inv = np.float64(1.0) / e
-        y = blk * inv
+        with np.errstate(over="ignore", divide="ignore"):
+            inv = np.float64(1.0) / e
+        y = blk / e if np.isinf(inv) else blk * inv
         t = np.trunc(y)
         frac = y - t                       # exact in binary floating point
         r = t + np.where(np.abs(frac) >= 0.5, np.sign(y), 0.0)
@@ -55,6 +56,22 @@ def test_ties_round_half_away_from_zero():
     c, e = O.compress(8, x, off)
     assert e[0] == 1.0
     assert list(c) == [127, 1, -1, 2, -2, 3, -3, 0, -127]
+
+
+def test_subnormal_scale():
+    """A block whose b_max is so small that 1/eps overflows is quantised by
+    division (same codes as the exact definition ANINT(x/eps))."""
+    x = np.array([2.67e-317, -1.1e-318, 0.0, -0.0, 1.3e-317])
+    off = np.array([0, len(x)], dtype=np.int64)
+    c, e = O.compress(16, x, off)
+    with np.errstate(divide="ignore", over="ignore"):
+        assert e[0] > 0 and np.isinf(1.0 / e[0])
+    assert c[2] == 0 and c[3] == 0 and np.all(np.abs(c) <= 32767)
+    # eps carries few significant bits here, so the largest code is not
+    # exactly qmax; the half-step bound still holds
+    assert np.all(np.abs(x - c * e[0]) <= e[0] / 2 + 1e-323)
+    c2, e2 = numpy_compress(16, x, off)
+    assert np.array_equal(c.astype(np.int64), c2) and np.array_equal(e, e2)
 
 
 def test_zero_block():
