@@ -163,3 +163,34 @@ def test_standalone_compress_decompress():
         assert np.array_equal(scales.cpu().numpy()[: len(sizes)], oe)
         assert np.array_equal(codes.cpu().numpy().astype(np.int32), oc)
         assert np.array_equal(out.cpu().numpy(), O.decompress(oc, oe, off))
+
+
+def test_full_size_sampled():
+    """The full 256-class workload (65536 quartets per class, the benchmark's
+    launch configuration): 96 seeded random quartets per class checked one by
+    one against the oracle, codes of those quartets against the oracle's
+    compressor."""
+    from paper_2303_13632_amd import eri
+    qpc = 65536
+    parts = [W.class_case(cid, n_quartets=qpc) for cid in range(256)]
+    shells, quartets = W.merge(parts)
+    del parts
+    plan = eri.Plan(shells, quartets, precision="fp64", bits=16)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(2024)
+    pick = np.concatenate([cid * qpc + np.sort(rng.choice(qpc, size=96, replace=False)) for cid in range(256)])
+    ref, ref_off, sizes = O.eri(shells, quartets[pick], n_threads=THREADS)
+    pos, eoff = plan.layout()
+    idx = np.concatenate([np.arange(eoff[t], eoff[t] + n) for t, n in zip(pick, sizes)])
+    got = e[torch.from_numpy(idx).cuda()].cpu().numpy()
+    codes = c[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int32)
+    scales = s[torch.from_numpy(pos[pick]).cuda()].cpu().numpy()
+    err = np.abs(got - ref)
+    print("full-size sample: %d quartets, max |err| %.3e" % (len(pick), err.max()))
+    assert np.all(err <= ABS_TOL + REL_TOL * np.abs(ref))
+    blk = _blocks(sizes)
+    oc, oe = O.compress(16, got, blk)
+    assert np.array_equal(oe, scales)
+    assert np.array_equal(oc, codes)
