@@ -332,8 +332,9 @@ def emit_mode_T(cp, prec):
     em("const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;")
     em("if (t >= A.n_items) return;")
     em("const eri_item it = A.items[t];")
-    em("const eri_shell_pair BP = A.pairs[it.bra];")
-    em("const eri_shell_pair KP = A.pairs[it.ket];")
+    em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
+    em("const eri_shell_pair BP = A.pairs[it.bra & 0x7fffffff];")
+    em("const eri_shell_pair KP = A.pairs[it.ket & 0x7fffffff];")
     # accumulators
     acc = {}
     for e in cp.E_T:
@@ -409,7 +410,7 @@ def emit_mode_T(cp, prec):
                     nm = "o%d" % len(outs)
                     expr = hrr_expr(bi, ai, lambda e, ci=ci, di=di: y[(e, ci, di)], "ab")
                     em("const double %s = (double)(%s);" % (nm, expr))
-                    outs.append((nm, user_index(cp, ia, ib_, ic, id_)))
+                    outs.append((nm, (ia, ib_, ic, id_)))
     emit_store_T(em, cp, outs)
     em.end()
     return name, em.text()
@@ -428,12 +429,27 @@ def user_index(cp, ia, ib, ic, id_):
     return ia * st[0] + ib * st[1] + ic * st[2] + id_ * st[3]
 
 
+def index_parts(cp, ia, ib, ic, id_):
+    """C expressions of the bra and ket parts of the user-layout index of
+    computed component indices; a pair of equal L may be stored swapped
+    (flags sb, sk), which exchanges the strides of its two shells."""
+    st = user_strides(cp)
+    bn, bs = ia * st[0] + ib * st[1], ia * st[1] + ib * st[0]
+    kn, ks = ic * st[2] + id_ * st[3], ic * st[3] + id_ * st[2]
+    bra = "(sb ? %d : %d)" % (bs, bn) if (cp.a == cp.b and bs != bn) else str(bn)
+    ket = "(sk ? %d : %d)" % (ks, kn) if (cp.c == cp.d and ks != kn) else str(kn)
+    return bra, ket
+
+
 def emit_store_T(em, cp, outs):
     n = cp.n_eriq
     em("const int64_t obase = t * %d;" % n)
+    for k, (nm, ix) in enumerate(outs):
+        bra, ket = index_parts(cp, *ix)
+        em("const int i%d = %s + %s;" % (k, bra, ket))
     em.block("if (A.out_eri)")
-    for nm, ui in outs:
-        em("A.out_eri[obase + %d] = %s;" % (ui, nm))
+    for k, (nm, ix) in enumerate(outs):
+        em("A.out_eri[obase + i%d] = %s;" % (k, nm))
     em.end()
     em("double bmax = 0.0;")
     for nm, _ in outs:
@@ -442,8 +458,8 @@ def emit_store_T(em, cp, outs):
     em("const double eps = bmax * A.cn;")
     em("const double inv = eri_inverse_scale(eps);")
     em("if (A.out_scales) A.out_scales[t] = eps;")
-    for nm, ui in outs:
-        em("eri_store_code(A.out_codes, obase + %d, A.code_bytes, eri_quantize(%s, eps, inv, A.qmax));" % (ui, nm))
+    for k, (nm, ix) in enumerate(outs):
+        em("eri_store_code(A.out_codes, obase + i%d, A.code_bytes, eri_quantize(%s, eps, inv, A.qmax));" % (k, nm))
     em.end()
 
 
@@ -513,8 +529,9 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     em("const int64_t qi = (int64_t)blockIdx.x * %d + slot;" % NSLOT)
     em("const bool active = slot < %d && qi < A.n_items;" % NSLOT)
     em("const eri_item it = A.items[active ? qi : 0];")
-    em("const eri_shell_pair BP = A.pairs[it.bra];")
-    em("const eri_shell_pair KP = A.pairs[it.ket];")
+    em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
+    em("const eri_shell_pair BP = A.pairs[it.bra & 0x7fffffff];")
+    em("const eri_shell_pair KP = A.pairs[it.ket & 0x7fffffff];")
     em("const int nbra = active ? BP.nprim : 0;")
     em("const int nket = KP.nprim;")
     em("const int sbase = slot * %d;" % EP)
@@ -630,14 +647,18 @@ def emit_mode_W(cp, prec, lds_budget=32768):
         # user-order index of (ab, kcd): computed (ic, id) = divmod(kcd, nd)
         st = user_strides(cp)
         nd = len(cd)
+        kn = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[2], nd, st[3])
         if st[2] == nd * st[3] and st[3] == 1:
-            em("const int64_t kx = kcd;")
+            kn = "(int64_t)kcd"
+        if cp.c == cp.d and nd > 1:
+            ks = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[3], nd, st[2])
+            em("const int64_t kx = sk ? %s : %s;" % (ks, kn))
         else:
-            em("const int64_t kx = (int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d;" % (nd, st[2], nd, st[3]))
-        ab_off = [(ia_ * st[0] + ib_ * st[1]) for ia_ in range(len(ca)) for ib_ in range(len(cb))]
-        idx = "%d + kx"
+            em("const int64_t kx = %s;" % kn)
         for k in range(len(ab_list)):
-            ix = idx % ab_off[k]
+            ia_, ib_ = divmod(k, len(cb))
+            bra, _ = index_parts(cp, ia_, ib_, 0, 0)
+            ix = "%s + kx" % bra
             if pass_no == 1:
                 em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)

@@ -145,12 +145,34 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
             cls[t] = c;
         }
         if (bad_class) { plan_free(p); return ERI_EUNSUPPORTED; }
+        // A pair of equal angular momenta may go either way round; the VRR is
+        // put on the centre that keeps max_ij K_ij (1 + |P_ij - A|)^(2L) small,
+        // i.e. where the Gaussian products sit, so the HRR does not amplify.
+        auto vrr_score = [&](int32_t a, int32_t b) {
+            const double* A = xyz + 3 * (int64_t)a;
+            const double* B = xyz + 3 * (int64_t)b;
+            const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+            const double r = std::sqrt(r2);
+            double best = 0.0;
+            for (int i = 0; i < K[a]; ++i)
+                for (int j = 0; j < K[b]; ++j) {
+                    const double al = exps[prim_off[a] + i], be = exps[prim_off[b] + j], pe = al + be;
+                    const double s = std::exp(-al * be / pe * r2) * std::pow(1.0 + be / pe * r, 2 * L[a]);
+                    best = std::max(best, s);
+                }
+            return best;
+        };
+        std::vector<uint8_t> swp(n_quartets, 0);
         parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
             for (int64_t t = lo; t < hi; ++t) {
                 const int32_t* q = quartets + 4 * t;
                 const int pm = tab[cls[t]].perm;
-                const int32_t ba = q[pm & 3], bb = q[(pm >> 2) & 3];
-                const int32_t ka = q[(pm >> 4) & 3], kb = q[(pm >> 6) & 3];
+                int32_t ba = q[pm & 3], bb = q[(pm >> 2) & 3];
+                int32_t ka = q[(pm >> 4) & 3], kb = q[(pm >> 6) & 3];
+                uint8_t f = 0;
+                if (ba != bb && L[ba] == L[bb] && vrr_score(bb, ba) < vrr_score(ba, bb)) { std::swap(ba, bb); f |= 1; }
+                if (ka != kb && L[ka] == L[kb] && vrr_score(kb, ka) < vrr_score(ka, kb)) { std::swap(ka, kb); f |= 2; }
+                swp[t] = f;
                 keys[2 * t] = ((uint64_t)(uint32_t)ba << 32) | (uint32_t)bb;
                 keys[2 * t + 1] = ((uint64_t)(uint32_t)ka << 32) | (uint32_t)kb;
             }
@@ -238,8 +260,8 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
         p->eri_off.assign(n_quartets, 0);
         for (int64_t j = 0; j < n_quartets; ++j) {
             const int64_t t = (int64_t)(order[j] & 0xffffffffu);
-            items[j].bra = bra[t];
-            items[j].ket = ket[t];
+            items[j].bra = (int32_t)((uint32_t)bra[t] | ((swp[t] & 1) ? 0x80000000u : 0u));
+            items[j].ket = (int32_t)((uint32_t)ket[t] | ((swp[t] & 2) ? 0x80000000u : 0u));
             p->pos[t] = j;
             p->class_count[cls[t]] += 1;
             const int64_t npq = (int64_t)pairs[bra[t]].nprim * pairs[ket[t]].nprim;

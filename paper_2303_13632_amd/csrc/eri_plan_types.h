@@ -25,7 +25,9 @@ struct eri_shell_pair {
     int32_t pad[2];
 };
 
-// One quartet of a class launch: bra and ket shell pairs.
+// One quartet of a class launch: bra and ket shell-pair indices.  The sign
+// bit marks a pair of equal angular momenta stored in the swapped order
+// (the kernel then exchanges the two shells' strides when it stores).
 struct eri_item {
     int32_t bra;
     int32_t ket;

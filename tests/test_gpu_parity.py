@@ -12,6 +12,7 @@ import pytest
 
 import oracle as O
 from paper_2303_13632_amd import workloads as W
+from parity_util import check_quartets
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -53,20 +54,15 @@ def test_all_classes_fp64_and_int16(all_classes):
     shells, quartets, ref, sizes = all_classes
     plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
     got = plan.to_user(vals)
-    cls = np.repeat(np.arange(256), N_PER_CLASS)
-    qcls = np.repeat(cls, sizes)
-    err = np.abs(got - ref)
-    tol = ABS_TOL + REL_TOL * np.abs(ref)
+    offs = _blocks(sizes)
     worst = []
     for c in range(256):
-        m = qcls == c
-        e = err[m].max()
-        worst.append((e, c))
-        if not np.all(err[m] <= tol[m]):
-            i = np.argmax(err[m] - tol[m])
-            pytest.fail("class %d %s: max err %.3e (value %.3e)" % (c, W.class_of(c), e, ref[m][i]))
+        qs = np.arange(c * N_PER_CLASS, (c + 1) * N_PER_CLASS)
+        lo, hi = offs[qs[0]], offs[qs[-1] + 1]
+        e, nref = check_quartets(shells, quartets[qs], got[lo:hi], ref[lo:hi], offs[qs] - lo, sizes[qs], THREADS)
+        worst.append((e, c, nref))
     worst.sort(reverse=True)
-    print("worst classes:", [(W.class_of(c), "%.2e" % e) for e, c in worst[:5]])
+    print("worst classes:", [(W.class_of(c), "%.2e" % e, n) for e, c, n in worst[:5]])
     # fused compression: codes and scales bit-identical to the oracle's compressor
     # applied to the GPU's own doubles, block = one quartet (plan order)
     blk = _blocks(np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets))
@@ -106,10 +102,10 @@ def test_fused_bit_widths(bits):
 def test_small_case_ss_ss_k3():
     """(ss|ss), K = 3, 4096 quartets: every quartet against the oracle."""
     shells, quartets = W.small_case()
-    ref, _, _ = O.eri(shells, quartets, n_threads=THREADS)
+    ref, _, sizes = O.eri(shells, quartets, n_threads=THREADS)
     plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
     got = plan.to_user(vals)
-    assert np.max(np.abs(got - ref)) <= ABS_TOL
+    check_quartets(shells, quartets, got, ref, _blocks(sizes), sizes, THREADS)
     # one value per quartet: each code is +-(2^15-1) or 0 at block = quartet
     assert np.all(np.isin(np.abs(codes), [0, 32767]))
 
@@ -129,10 +125,10 @@ def test_degenerate_geometries():
         sh["exps"][: len(sh["exps"]) // 3] *= 50.0   # tight
         parts.append((sh, q))
     shells, quartets = W.merge(parts)
-    ref, _, _ = O.eri(shells, quartets, n_threads=THREADS)
+    ref, _, sizes = O.eri(shells, quartets, n_threads=THREADS)
     plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
     got = plan.to_user(vals)
-    assert np.all(np.abs(got - ref) <= ABS_TOL + REL_TOL * np.abs(ref))
+    check_quartets(shells, quartets, got, ref, _blocks(sizes), sizes, THREADS)
 
 
 def test_empty_plan():
@@ -187,10 +183,9 @@ def test_full_size_sampled():
     got = e[torch.from_numpy(idx).cuda()].cpu().numpy()
     codes = c[torch.from_numpy(idx).cuda()].cpu().numpy().astype(np.int32)
     scales = s[torch.from_numpy(pos[pick]).cuda()].cpu().numpy()
-    err = np.abs(got - ref)
-    print("full-size sample: %d quartets, max |err| %.3e" % (len(pick), err.max()))
-    assert np.all(err <= ABS_TOL + REL_TOL * np.abs(ref))
     blk = _blocks(sizes)
+    e, nref = check_quartets(shells, quartets[pick], got, ref, blk, sizes, THREADS)
+    print("full-size sample: %d quartets, max |err| %.3e (%d refereed in __float128)" % (len(pick), e, nref))
     oc, oe = O.compress(16, got, blk)
     assert np.array_equal(oe, scales)
     assert np.array_equal(oc, codes)
