@@ -63,11 +63,16 @@ extern "C" {
 
 typedef struct eri_plan eri_plan;
 
+#define ERI_PLAN_ALL_QUARTETS 1  /* plan every unique Schwarz-screened quartet of the shell set */
+
 typedef struct {
-    int32_t precision;   /* ERI_FP64 or ERI_FP32_MIXED */
-    int32_t bits;        /* code width n of eq. 10: 0 = no codes, else 2..32 */
-    int32_t device;      /* HIP device ordinal */
-    int32_t reserved;
+    int32_t precision;          /* ERI_FP64 or ERI_FP32_MIXED */
+    int32_t bits;               /* code width n of eq. 10: 0 = no codes, else 2..32 */
+    int32_t device;             /* HIP device ordinal */
+    int32_t flags;              /* ERI_PLAN_ALL_QUARTETS or 0 */
+    double schwarz_threshold;   /* with ERI_PLAN_ALL_QUARTETS: keep (ab|cd) with Q_ab Q_cd >= this */
+    int64_t ring_bytes;         /* with ERI_PLAN_ALL_QUARTETS: bound on the output held (0 = all) */
+    int64_t chunk_quartets;     /* with ERI_PLAN_ALL_QUARTETS: quartets per launch chunk (0 = 2^25) */
 } eri_plan_opts;
 
 typedef struct {
@@ -79,7 +84,10 @@ typedef struct {
     int64_t device_bytes;       /* device memory held by the plan */
     int32_t code_bytes;         /* 0, 1, 2 or 4 */
     int32_t bits;
+    int32_t batched;            /* 1 for ERI_PLAN_ALL_QUARTETS plans */
+    int32_t reserved;
     int64_t class_quartets[256];  /* quartets per class */
+    int64_t class_ring[256];      /* output slots per class (== quartets unless a ring bound applies) */
     int64_t class_eri_off[257];   /* first ERI of each class in plan order */
     int64_t class_quartet_off[257];
     double class_flops[256];      /* algorithmic FLOPs of each class launch */
@@ -89,6 +97,15 @@ typedef struct {
  * the host the shell-pair and primitive-pair data the kernels read (Gaussian
  * product centre, exponent sums, prefactors), sorts the quartets into plan
  * order and uploads everything to `opts->device`.
+ * With opts->flags = ERI_PLAN_ALL_QUARTETS (quartets = NULL, n_quartets = 0)
+ * the plan covers every unique quartet (ab|cd), a >= b, c >= d, (ab) >= (cd),
+ * whose Schwarz bound Q_ab Q_cd, Q_ab = sqrt(max_mu (mu|mu)) over the pair's
+ * components, reaches opts->schwarz_threshold; the Q_ab are computed on the
+ * GPU by the same kernels.  Such a plan keeps per-class pair lists sorted by
+ * Q and expands the quartets on the device in chunks of opts->chunk_quartets;
+ * its outputs form, per class, a ring of class_ring[c] quartet slots (quartet
+ * j of class c lands in slot j mod class_ring[c]); opts->ring_bytes bounds the
+ * total (codes, or FP64 values when bits = 0).
  * Returns ERI_EINVAL for null pointers or indices outside [0, n_shells),
  * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K] or a bad `bits`,
  * ERI_ENOMEM / ERI_EHIP on allocation or upload failure.  On success *out owns
@@ -103,15 +120,25 @@ int eri_plan_info_get(const eri_plan* plan, eri_plan_info* info);
 
 /* Plan-order layout: for user quartet t, pos[t] is its plan position, so its
  * values start at eri_off[t] (ERIs) and its scale is scales[pos[t]].  Both
- * arrays are host memory of length n_quartets. */
+ * arrays are host memory of length n_quartets.  ERI_ESTATE for
+ * ERI_PLAN_ALL_QUARTETS plans (use eri_plan_quartets). */
 int eri_plan_layout(const eri_plan* plan, int64_t* pos, int64_t* eri_off);
 
+/* Shell indices (a, b, c, d) of quartets [first, first + count) of class
+ * class_id, in the order their outputs are written (host int32, 4 per
+ * quartet).  For explicit plans these are the user quartets in plan order. */
+int eri_plan_quartets(const eri_plan* plan, int32_t class_id, int64_t first, int64_t count, int32_t* out);
+
 /* Compute every quartet of the plan on `stream` (Sec. II-B..II-D): contracted
- * ERIs; when out_eri is not NULL they are written as FP64 (n_eri doubles);
- * when the plan has bits > 0 and out_codes is not NULL, each quartet is
- * compressed with its own b_max (eqs. 9-10): n_eri codes and n_quartets FP64
- * scales eps (out_scales, required with codes).  Device pointers, plan order.
- * Returns ERI_EINVAL if no output is requested. */
+ * ERIs; when out_eri is not NULL they are written as FP64; when the plan has
+ * bits > 0 and out_codes is not NULL, each quartet is compressed with its own
+ * b_max (eqs. 9-10) into codes plus one FP64 scale eps (out_scales, required
+ * with codes).  Device pointers, plan order; the arrays hold
+ * class_eri_off[256] values/codes and class_quartet_off[256] scales (equal to
+ * n_eri and n_quartets unless a ring bound applies).
+ * Returns ERI_EINVAL if no output is requested.  For ERI_PLAN_ALL_QUARTETS
+ * plans all launches are captured once into a hipGraph (per output pointer
+ * set) and replayed as a single graph launch. */
 int eri_compute(eri_plan* plan, void* stream, double* out_eri, void* out_codes, double* out_scales);
 
 /* Same as eri_compute for the quartets of one class only (class id

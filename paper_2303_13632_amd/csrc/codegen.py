@@ -441,9 +441,16 @@ def index_parts(cp, ia, ib, ic, id_):
     return bra, ket
 
 
+def emit_slot(em, idx):
+    """Output slot of launch item `idx`: class quartet qbase + idx in a ring."""
+    em("const int64_t gq = A.qbase + %s;" % idx)
+    em("const int64_t oslot = gq < A.ring ? gq : gq % A.ring;")
+
+
 def emit_store_T(em, cp, outs):
     n = cp.n_eriq
-    em("const int64_t obase = t * %d;" % n)
+    emit_slot(em, "t")
+    em("const int64_t obase = oslot * %d;" % n)
     for k, (nm, ix) in enumerate(outs):
         bra, ket = index_parts(cp, *ix)
         em("const int i%d = %s + %s;" % (k, bra, ket))
@@ -457,7 +464,7 @@ def emit_store_T(em, cp, outs):
     em.block("if (A.out_codes)")
     em("const double eps = bmax * A.cn;")
     em("const double inv = eri_inverse_scale(eps);")
-    em("if (A.out_scales) A.out_scales[t] = eps;")
+    em("if (A.out_scales) A.out_scales[oslot] = eps;")
     for k, (nm, ix) in enumerate(outs):
         em("eri_store_code(A.out_codes, obase + i%d, A.code_bytes, eri_quantize(%s, eps, inv, A.qmax));" % (k, nm))
     em.end()
@@ -586,16 +593,24 @@ def emit_mode_W(cp, prec, lds_budget=32768):
             em.end()
     # ket VRR: values V_s(f, m), m <= Lcd - |f|
     V = {}
+    # Level order (all f of |f| = k before k + 1): the elements of a level are
+    # independent, which gives the scheduler room to hide the permute latency.
+    # (A depth-first order along x-chains needs fewer live columns but makes
+    # every element wait for the permute of the one before it.)
     kets = [f for L in range(cp.Lcd + 1) for f in comps(L)]
+    tset = set(cp.F_T)
     for s in range(S):
         for m in range(cp.Lcd + 1):
             V[(s, ZERO, m)] = "c%d[%d]" % (s, m)
     nvar = 0
     for f in kets:
         if f == ZERO:
+            if ZERO in tset:
+                for s in range(S):
+                    em("%s += %s;" % (acc[(s, f)], ("(double)" + V[(s, f, 0)]) if mixed else V[(s, f, 0)]))
             continue
         L = sum(f)
-        i = lower_dir(f, cp.rule)
+        i = 0 if f[0] > 0 else (1 if f[1] > 0 else 2)
         ax = "xyz"[i]
         fp = vsub(f, UNIT[i])
         for m in range(cp.Lcd - L + 1):
@@ -610,14 +625,15 @@ def emit_mode_W(cp, prec, lds_budget=32768):
                 expr += " + ce%s%d * __shfl(%s, s%s%d)" % (ax, s, V[(ss, fp, m + 1)], ax, s)
                 em("const %s %s = %s;" % (real, nm, expr))
                 V[(s, f, m)] = nm
-    for s in range(S):
-        for f in cp.F_T:
-            v = V[(s, f, 0)]
-            em("%s += %s;" % (acc[(s, f)], ("(double)" + v) if mixed else v))
+        if f in tset:
+            for s in range(S):
+                v = V[(s, f, 0)]
+                em("%s += %s;" % (acc[(s, f)], ("(double)" + v) if mixed else v))
     em.end()
     em.end()
     # HRR
-    em("const int64_t obase = qi * %d;" % cp.n_eriq)
+    emit_slot(em, "qi")
+    em("const int64_t obase = oslot * %d;" % cp.n_eriq)
     emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
     emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
     cd_list = [(ci, di) for ci in cc for di in cd]
@@ -679,7 +695,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     em("if (slot < %d) for (int k = 0; k < %d; ++k) m = fmax(m, s_red[sbase + k]);" % (NSLOT, EP))
     em("const double eps = m * A.cn;")
     em("const double inv = eri_inverse_scale(eps);")
-    em("if (active && ls == 0 && A.out_scales) A.out_scales[qi] = eps;")
+    em("if (active && ls == 0 && A.out_scales) A.out_scales[oslot] = eps;")
     for ch in range(NCH):
         ket_hrr_chunk(ch)
         bra_hrr_chunk(ch, 2)

@@ -1,6 +1,8 @@
-// Host side of the ERI library: plan builder (shell-pair / primitive-pair
-// tables, class-sorted work lists), launches of the generated class kernels,
-// the standalone compression kernels and the C ABI of include/eri.h.
+// Host side of the ERI library: plan builders (shell-pair / primitive-pair
+// tables, class-sorted work lists, Schwarz-screened batched work over a whole
+// shell set), launches of the generated class kernels (captured in a hipGraph
+// for batched plans), the standalone compression kernels and the C ABI of
+// include/eri.h.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,13 +23,19 @@ namespace {
 
 thread_local int g_last_hip = 0;
 
-#define ERI_HIP_TRY(expr)                         \
-    do {                                          \
-        hipError_t _e = (expr);                   \
-        if (_e != hipSuccess) {                   \
-            g_last_hip = (int)_e;                 \
-            return _e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP; \
-        }                                         \
+#define ERI_HIP_TRY(expr)                                                  \
+    do {                                                                   \
+        hipError_t _e = (expr);                                            \
+        if (_e != hipSuccess) {                                            \
+            g_last_hip = (int)_e;                                          \
+            return _e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP;      \
+        }                                                                  \
+    } while (0)
+
+#define ERI_TRY(expr)                  \
+    do {                               \
+        int _rc = (expr);              \
+        if (_rc != ERI_OK) return _rc; \
     } while (0)
 
 inline int ncart(int L) { return (L + 1) * (L + 2) / 2; }
@@ -60,7 +68,107 @@ void parallel_for(int64_t n, F f)
     for (auto& x : th) x.join();
 }
 
+// Host view of the caller's shell set.
+struct shell_set {
+    int64_t n;
+    const int32_t* L;
+    const int32_t* K;
+    const double* xyz;
+    const int64_t* off;
+    const double* exps;
+    const double* coefs;
+};
+
+// A pair of equal angular momenta may go either way round; the VRR is put on
+// the centre that keeps max_ij K_ij (1 + |P_ij - A|)^(2L) small, i.e. where
+// the Gaussian products sit, so the HRR does not amplify rounding.
+double vrr_score(const shell_set& s, int32_t a, int32_t b)
+{
+    const double* A = s.xyz + 3 * (int64_t)a;
+    const double* B = s.xyz + 3 * (int64_t)b;
+    const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    const double r = std::sqrt(r2);
+    double best = 0.0;
+    for (int i = 0; i < s.K[a]; ++i)
+        for (int j = 0; j < s.K[b]; ++j) {
+            const double al = s.exps[s.off[a] + i], be = s.exps[s.off[b] + j], pe = al + be;
+            best = std::max(best, std::exp(-al * be / pe * r2) * std::pow(1.0 + be / pe * r, 2 * s.L[a]));
+        }
+    return best;
+}
+
+// Shell-pair records and their primitive-pair records for ordered pairs
+// keys[i] = (a << 32) | b.
+void build_pair_tables(const shell_set& s, const std::vector<uint64_t>& keys, std::vector<eri_shell_pair>& pairs,
+                       std::vector<eri_prim_pair>& prims)
+{
+    const int64_t npair = (int64_t)keys.size();
+    pairs.assign(npair, eri_shell_pair());
+    int64_t nprim = 0;
+    for (int64_t i = 0; i < npair; ++i) {
+        const int32_t sa = (int32_t)(keys[i] >> 32), sb = (int32_t)(keys[i] & 0xffffffffu);
+        eri_shell_pair& sp = pairs[i];
+        for (int x = 0; x < 3; ++x) sp.AB[x] = s.xyz[3 * (int64_t)sa + x] - s.xyz[3 * (int64_t)sb + x];
+        sp.prim_off = nprim;
+        sp.nprim = s.K[sa] * s.K[sb];
+        sp.kb = s.K[sb];
+        sp.sa = sa;
+        sp.sb = sb;
+        sp.pad[0] = sp.pad[1] = 0;
+        nprim += sp.nprim;
+    }
+    // c_k N(alpha_k, L) of every primitive of every shell
+    std::vector<int64_t> first(s.n + 1, 0);
+    for (int64_t sh = 0; sh < s.n; ++sh) first[sh + 1] = first[sh] + s.K[sh];
+    std::vector<double> cnorm(first[s.n]);
+    parallel_for(s.n, [&](int64_t lo, int64_t hi) {
+        for (int64_t sh = lo; sh < hi; ++sh)
+            for (int k = 0; k < s.K[sh]; ++k)
+                cnorm[first[sh] + k] = s.coefs[s.off[sh] + k] * norm_axis(s.exps[s.off[sh] + k], s.L[sh]);
+    });
+    prims.assign(nprim, eri_prim_pair());
+    parallel_for(npair, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const eri_shell_pair& sp = pairs[i];
+            const int32_t sa = sp.sa, sb = sp.sb;
+            const double* A = s.xyz + 3 * (int64_t)sa;
+            const double* B = s.xyz + 3 * (int64_t)sb;
+            const double ab2 = sp.AB[0] * sp.AB[0] + sp.AB[1] * sp.AB[1] + sp.AB[2] * sp.AB[2];
+            for (int ia = 0; ia < s.K[sa]; ++ia)
+                for (int ib = 0; ib < s.K[sb]; ++ib) {
+                    const double al = s.exps[s.off[sa] + ia], be = s.exps[s.off[sb] + ib];
+                    eri_prim_pair& pp = prims[sp.prim_off + ia * s.K[sb] + ib];
+                    const double pe = al + be;
+                    pp.p = pe;
+                    pp.hp = 0.5 / pe;
+                    const double kab = cnorm[first[sa] + ia] * cnorm[first[sb] + ib] * std::exp(-al * be / pe * ab2);
+                    pp.kp = kab / pe;
+                    for (int x = 0; x < 3; ++x) {
+                        pp.P[x] = (al * A[x] + be * B[x]) / pe;
+                        pp.PA[x] = pp.P[x] - A[x];
+                    }
+                    pp.alpha = al;
+                    pp.beta = be;
+                    pp.pad = 0.0;
+                }
+        }
+    });
+}
+
 }  // namespace
+
+// One batched class: the quartets (P1 | P2) of a bra pair class and a ket
+// pair class, enumerated as segments: for each bra pair P1 a prefix of the
+// Q-sorted ket pair list.
+struct eri_batch_class {
+    int cid = -1;
+    bool swap = false;              // kernel's computed bra is P2
+    int64_t n_quartets = 0;
+    int64_t seg_lo = 0, seg_hi = 0; // range in the plan's segment arrays
+    int64_t ket_lo = 0;             // first ket pair (global index) of the ket class
+    int64_t ring = 0;               // output slots
+    std::vector<int64_t> chunk_seg; // segment boundaries of the launch chunks
+};
 
 struct eri_plan {
     int device = 0;
@@ -68,18 +176,33 @@ struct eri_plan {
     int bits = 0;
     int code_bytes = 0;
     double cn = 0.0, qmax = 0.0;
+    bool batched = false;
     int64_t n_quartets = 0, n_eri = 0, n_prim_quartets = 0;
-    std::vector<int64_t> pos;       // user quartet -> plan position
-    std::vector<int64_t> eri_off;   // user quartet -> first ERI
+    std::vector<int64_t> pos;       // explicit plans: user quartet -> plan position
+    std::vector<int64_t> eri_off;   // explicit plans: user quartet -> first ERI
+    std::vector<int32_t> quartets;  // explicit plans: user quartets in plan order
     int64_t class_count[256] = {};
+    int64_t class_ring[256] = {};
     int64_t class_qoff[257] = {};
     int64_t class_eoff[257] = {};
     double class_flops[256] = {};
     int64_t n_pairs = 0, n_prims = 0;
+    std::vector<eri_shell_pair> h_pairs;   // batched plans keep the pair table on the host
     eri_shell_pair* d_pairs = nullptr;
     eri_prim_pair* d_prims = nullptr;
     eri_item* d_items = nullptr;
     int64_t device_bytes = 0;
+    // batched plans
+    std::vector<eri_batch_class> bclass;
+    std::vector<int64_t> h_seg_off;     // quartet offset of each segment within its class
+    std::vector<int32_t> h_seg_p1;
+    int64_t* d_seg_off = nullptr;
+    int32_t* d_seg_p1 = nullptr;
+    int64_t chunk_cap = 0;
+    double schwarz = 0.0;
+    std::vector<double> pair_q;
+    hipGraphExec_t graph = nullptr;
+    const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 static const eri_kernel_info* kernel_table(int precision)
@@ -92,11 +215,347 @@ static void plan_free(eri_plan* p)
     if (!p) return;
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->d_pairs) (void)hipFree(p->d_pairs);
     if (p->d_prims) (void)hipFree(p->d_prims);
     if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_seg_off) (void)hipFree(p->d_seg_off);
+    if (p->d_seg_p1) (void)hipFree(p->d_seg_p1);
     if (cur != p->device) (void)hipSetDevice(cur);
     delete p;
+}
+
+static int upload(eri_plan* p, void** dst, const void* src, size_t bytes)
+{
+    if (bytes == 0) bytes = 64;
+    hipError_t e = hipMalloc(dst, bytes);
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        g_last_hip = (int)e;
+        return e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP;
+    }
+    p->device_bytes += (int64_t)bytes;
+    if (src) {
+        e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            return ERI_EHIP;
+        }
+    }
+    return ERI_OK;
+}
+
+static int check_shells(const shell_set& s)
+{
+    if (s.n > 0 && (!s.L || !s.K || !s.xyz || !s.off || !s.exps || !s.coefs)) return ERI_EINVAL;
+    if (s.n > INT32_MAX) return ERI_EUNSUPPORTED;
+    for (int64_t i = 0; i < s.n; ++i) {
+        if (s.L[i] < 0 || s.L[i] > ERI_MAX_L || s.K[i] < 1 || s.K[i] > ERI_MAX_K) return ERI_EUNSUPPORTED;
+        if (s.off[i] < 0) return ERI_EINVAL;
+        for (int k = 0; k < s.K[i]; ++k)
+            if (!(s.exps[s.off[i] + k] > 0.0)) return ERI_EINVAL;
+    }
+    return ERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Explicit quartet lists
+// ---------------------------------------------------------------------------
+static int create_explicit(eri_plan* p, const shell_set& s, const int32_t* quartets, int64_t n_quartets)
+{
+    const eri_kernel_info* tab = kernel_table(p->precision);
+    p->n_quartets = n_quartets;
+    std::vector<int32_t> cls(n_quartets);
+    std::vector<uint64_t> keys(2 * n_quartets);
+    for (int64_t t = 0; t < n_quartets; ++t) {
+        const int32_t* q = quartets + 4 * t;
+        const int c = s.L[q[0]] * 64 + s.L[q[1]] * 16 + s.L[q[2]] * 4 + s.L[q[3]];
+        if (!tab[c].fn) return ERI_EUNSUPPORTED;
+        cls[t] = c;
+    }
+    std::vector<uint8_t> swp(n_quartets, 0);
+    parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
+        for (int64_t t = lo; t < hi; ++t) {
+            const int32_t* q = quartets + 4 * t;
+            const int pm = tab[cls[t]].perm;
+            int32_t ba = q[pm & 3], bb = q[(pm >> 2) & 3];
+            int32_t ka = q[(pm >> 4) & 3], kb = q[(pm >> 6) & 3];
+            uint8_t f = 0;
+            if (ba != bb && s.L[ba] == s.L[bb] && vrr_score(s, bb, ba) < vrr_score(s, ba, bb)) { std::swap(ba, bb); f |= 1; }
+            if (ka != kb && s.L[ka] == s.L[kb] && vrr_score(s, kb, ka) < vrr_score(s, ka, kb)) { std::swap(ka, kb); f |= 2; }
+            swp[t] = f;
+            keys[2 * t] = ((uint64_t)(uint32_t)ba << 32) | (uint32_t)bb;
+            keys[2 * t + 1] = ((uint64_t)(uint32_t)ka << 32) | (uint32_t)kb;
+        }
+    });
+    std::vector<uint64_t> uniq(keys);
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    if ((int64_t)uniq.size() > INT32_MAX) return ERI_EUNSUPPORTED;
+    std::vector<eri_shell_pair> pairs;
+    std::vector<eri_prim_pair> prims;
+    build_pair_tables(s, uniq, pairs, prims);
+    std::vector<int32_t> bra(n_quartets), ket(n_quartets);
+    parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
+        for (int64_t t = lo; t < hi; ++t) {
+            bra[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[2 * t]) - uniq.begin());
+            ket[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[2 * t + 1]) - uniq.begin());
+        }
+    });
+    std::vector<uint64_t>().swap(uniq);
+    std::vector<uint64_t>().swap(keys);
+    // plan order: class (8 bits), bra and ket primitive counts (9 bits each),
+    // then the user index (32 bits): a plain sort is stable in user order
+    if (n_quartets > (int64_t)UINT32_MAX) return ERI_EUNSUPPORTED;
+    std::vector<uint64_t> order(n_quartets);
+    parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
+        for (int64_t t = lo; t < hi; ++t) {
+            const uint64_t nb = (uint64_t)std::min(pairs[bra[t]].nprim, 511);
+            const uint64_t nk = (uint64_t)std::min(pairs[ket[t]].nprim, 511);
+            order[t] = ((uint64_t)cls[t] << 50) | (nb << 41) | (nk << 32) | (uint64_t)t;
+        }
+    });
+    std::sort(order.begin(), order.end());
+    std::vector<eri_item> items(n_quartets);
+    p->pos.assign(n_quartets, 0);
+    p->eri_off.assign(n_quartets, 0);
+    p->quartets.assign(4 * n_quartets, 0);
+    for (int64_t j = 0; j < n_quartets; ++j) {
+        const int64_t t = (int64_t)(order[j] & 0xffffffffu);
+        items[j].bra = (int32_t)((uint32_t)bra[t] | ((swp[t] & 1) ? 0x80000000u : 0u));
+        items[j].ket = (int32_t)((uint32_t)ket[t] | ((swp[t] & 2) ? 0x80000000u : 0u));
+        p->pos[t] = j;
+        for (int k = 0; k < 4; ++k) p->quartets[4 * j + k] = quartets[4 * t + k];
+        p->class_count[cls[t]] += 1;
+        const int64_t npq = (int64_t)pairs[bra[t]].nprim * pairs[ket[t]].nprim;
+        p->n_prim_quartets += npq;
+        p->class_flops[cls[t]] += (double)npq * tab[cls[t]].flops_pq + (double)tab[cls[t]].flops_q;
+    }
+    p->class_qoff[0] = 0;
+    p->class_eoff[0] = 0;
+    for (int c = 0; c < 256; ++c) {
+        p->class_ring[c] = p->class_count[c];
+        p->class_qoff[c + 1] = p->class_qoff[c] + p->class_count[c];
+        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_count[c] * (int64_t)tab[c].n_eriq;
+    }
+    p->n_eri = p->class_eoff[256];
+    for (int64_t t = 0; t < n_quartets; ++t) {
+        const int c = cls[t];
+        p->eri_off[t] = p->class_eoff[c] + (p->pos[t] - p->class_qoff[c]) * (int64_t)tab[c].n_eriq;
+    }
+    p->n_pairs = (int64_t)pairs.size();
+    p->n_prims = (int64_t)prims.size();
+    ERI_TRY(upload(p, (void**)&p->d_pairs, pairs.empty() ? nullptr : pairs.data(), pairs.size() * sizeof(eri_shell_pair)));
+    ERI_TRY(upload(p, (void**)&p->d_prims, prims.empty() ? nullptr : prims.data(), prims.size() * sizeof(eri_prim_pair)));
+    ERI_TRY(upload(p, (void**)&p->d_items, items.empty() ? nullptr : items.data(), items.size() * sizeof(eri_item)));
+    return ERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched plans: all unique Schwarz-screened quartets of a shell set
+// ---------------------------------------------------------------------------
+// Writes the items (computed bra, computed ket) of segments [seg_lo, seg_lo +
+// gridDim.x) of one class; seg_off holds quartet offsets within the class.
+__global__ __launch_bounds__(256) void eri_expand_kernel(const int64_t* __restrict__ seg_off,
+                                                         const int32_t* __restrict__ seg_p1, int64_t seg_lo,
+                                                         int64_t ket_lo, int64_t q_lo, int swap,
+                                                         eri_item* __restrict__ items)
+{
+    const int64_t s = seg_lo + blockIdx.x;
+    const int64_t beg = seg_off[s], end = seg_off[s + 1];
+    const int32_t p1 = seg_p1[s];
+    for (int64_t t = beg + threadIdx.x; t < end; t += 256) {
+        const int32_t p2 = (int32_t)(ket_lo + (t - beg));
+        eri_item it;
+        it.bra = swap ? p2 : p1;
+        it.ket = swap ? p1 : p2;
+        items[t - q_lo] = it;
+    }
+}
+
+static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* o)
+{
+    const eri_kernel_info* tab = kernel_table(p->precision);
+    p->batched = true;
+    p->schwarz = o->schwarz_threshold;
+    // ---- canonical pairs a >= b (shell index), larger L first ---------------
+    std::vector<uint64_t> keys;
+    keys.reserve((size_t)(s.n * (s.n + 1) / 2));
+    for (int64_t a = 0; a < s.n; ++a)
+        for (int64_t b = 0; b <= a; ++b) {
+            int32_t x = (int32_t)a, y = (int32_t)b;
+            if (s.L[y] > s.L[x]) std::swap(x, y);
+            keys.push_back(((uint64_t)(uint32_t)x << 32) | (uint32_t)y);
+        }
+    parallel_for((int64_t)keys.size(), [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            const int32_t x = (int32_t)(keys[i] >> 32), y = (int32_t)(keys[i] & 0xffffffffu);
+            if (x != y && s.L[x] == s.L[y] && vrr_score(s, y, x) < vrr_score(s, x, y))
+                keys[i] = ((uint64_t)(uint32_t)y << 32) | (uint32_t)x;
+        }
+    });
+    // ---- Schwarz factors Q_ab = sqrt(max_mu (mu|mu)) from the GPU ------------
+    std::vector<double> Q(keys.size(), 0.0);
+    {
+        std::vector<int32_t> dq(4 * keys.size());
+        for (size_t i = 0; i < keys.size(); ++i) {
+            const int32_t x = (int32_t)(keys[i] >> 32), y = (int32_t)(keys[i] & 0xffffffffu);
+            dq[4 * i] = x; dq[4 * i + 1] = y; dq[4 * i + 2] = x; dq[4 * i + 3] = y;
+        }
+        eri_plan_opts d = *o;
+        d.precision = ERI_FP64;
+        d.bits = 0;
+        d.flags = 0;
+        eri_plan* dp = nullptr;
+        ERI_TRY(eri_plan_create(&dp, s.n, s.L, s.K, s.xyz, s.off, s.exps, s.coefs, dq.data(), (int64_t)keys.size(), &d));
+        double* dv = nullptr;
+        int rc = ERI_OK;
+        hipError_t e = hipMalloc((void**)&dv, (size_t)std::max<int64_t>(dp->n_eri, 1) * sizeof(double));
+        if (e != hipSuccess) { g_last_hip = (int)e; rc = e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP; }
+        if (rc == ERI_OK) rc = eri_compute(dp, nullptr, dv, nullptr, nullptr);
+        std::vector<double> hv;
+        if (rc == ERI_OK) {
+            try { hv.resize(dp->n_eri); } catch (const std::bad_alloc&) { rc = ERI_ENOMEM; }
+        }
+        if (rc == ERI_OK) {
+            e = hipMemcpy(hv.data(), dv, hv.size() * sizeof(double), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) { g_last_hip = (int)e; rc = ERI_EHIP; }
+        }
+        if (dv) (void)hipFree(dv);
+        if (rc == ERI_OK) {
+            for (size_t i = 0; i < keys.size(); ++i) {
+                const int32_t x = (int32_t)(keys[i] >> 32), y = (int32_t)(keys[i] & 0xffffffffu);
+                const int n = ncart(s.L[x]) * ncart(s.L[y]);
+                const double* v = hv.data() + dp->eri_off[i];
+                double m = 0.0;
+                for (int k = 0; k < n; ++k) m = std::max(m, std::fabs(v[(int64_t)k * n + k]));
+                Q[i] = std::sqrt(m);
+            }
+        }
+        eri_plan_destroy(dp);
+        if (rc != ERI_OK) return rc;
+    }
+    const double qmax_all = Q.empty() ? 0.0 : *std::max_element(Q.begin(), Q.end());
+    // ---- pair classes (La, Lb), pairs Q-sorted within a class --------------
+    std::vector<int64_t> order;
+    for (size_t i = 0; i < keys.size(); ++i)
+        if (Q[i] * qmax_all >= p->schwarz && Q[i] > 0.0) order.push_back((int64_t)i);
+    auto pclass = [&](int64_t i) {
+        const int32_t x = (int32_t)(keys[i] >> 32), y = (int32_t)(keys[i] & 0xffffffffu);
+        return s.L[x] * 4 + s.L[y];
+    };
+    std::sort(order.begin(), order.end(), [&](int64_t u, int64_t v) {
+        const int cu = pclass(u), cv = pclass(v);
+        if (cu != cv) return cu < cv;
+        if (Q[u] != Q[v]) return Q[u] > Q[v];
+        return u < v;
+    });
+    if ((int64_t)order.size() > INT32_MAX) return ERI_EUNSUPPORTED;
+    std::vector<uint64_t> skeys(order.size());
+    p->pair_q.resize(order.size());
+    int64_t cls_lo[17];
+    for (int c = 0; c <= 16; ++c) cls_lo[c] = 0;
+    for (size_t j = 0; j < order.size(); ++j) {
+        skeys[j] = keys[order[j]];
+        p->pair_q[j] = Q[order[j]];
+        cls_lo[pclass(order[j]) + 1] += 1;
+    }
+    for (int c = 0; c < 16; ++c) cls_lo[c + 1] += cls_lo[c];
+    std::vector<eri_prim_pair> prims;
+    build_pair_tables(s, skeys, p->h_pairs, prims);
+    p->n_pairs = (int64_t)p->h_pairs.size();
+    p->n_prims = (int64_t)prims.size();
+    // ---- segments: for each bra pair P1, the prefix of ket pairs P2 with
+    //      Q1 Q2 >= tau (and P2 <= P1 inside one pair class) ------------------
+    const int64_t cap = o->chunk_quartets > 0 ? o->chunk_quartets : ((int64_t)1 << 25);
+    p->chunk_cap = cap;
+    int64_t maxchunk = 1;
+    for (int cb = 0; cb < 16; ++cb) {
+        for (int ck = 0; ck <= cb; ++ck) {
+            const int64_t b0 = cls_lo[cb], b1 = cls_lo[cb + 1], k0 = cls_lo[ck], k1 = cls_lo[ck + 1];
+            if (b0 == b1 || k0 == k1) continue;
+            const int cid = (cb / 4) * 64 + (cb % 4) * 16 + (ck / 4) * 4 + (ck % 4);
+            if (!tab[cid].fn) return ERI_EUNSUPPORTED;
+            eri_batch_class bc;
+            bc.cid = cid;
+            bc.swap = (tab[cid].perm & 3) >= 2;
+            bc.ket_lo = k0;
+            bc.seg_lo = (int64_t)p->h_seg_p1.size();
+            int64_t q = 0;
+            double flops = 0.0;
+            std::vector<int64_t> kprim(k1 - k0 + 1, 0);
+            for (int64_t k = k0; k < k1; ++k) kprim[k - k0 + 1] = kprim[k - k0] + p->h_pairs[k].nprim;
+            for (int64_t b = b0; b < b1; ++b) {
+                const double need = p->schwarz / p->pair_q[b];
+                // ket pairs are sorted by decreasing Q: count those with Q >= need
+                int64_t lo = k0, hi = k1;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) / 2;
+                    if (p->pair_q[mid] >= need) lo = mid + 1; else hi = mid;
+                }
+                int64_t n = lo - k0;
+                if (cb == ck) n = std::min(n, b - b0 + 1);
+                if (n <= 0) continue;
+                if (n > cap) return ERI_EUNSUPPORTED;
+                p->h_seg_off.push_back(q);
+                p->h_seg_p1.push_back((int32_t)b);
+                q += n;
+                const int64_t npq = (int64_t)p->h_pairs[b].nprim * kprim[n];
+                p->n_prim_quartets += npq;
+                flops += (double)npq * tab[cid].flops_pq + (double)n * tab[cid].flops_q;
+            }
+            bc.seg_hi = (int64_t)p->h_seg_p1.size();
+            if (bc.seg_hi == bc.seg_lo) continue;
+            // closing entry of the class: seg_off[seg_hi] = total quartets
+            p->h_seg_off.push_back(q);
+            p->h_seg_p1.push_back(-1);
+            bc.n_quartets = q;
+            p->class_count[cid] = q;
+            p->class_flops[cid] = flops;
+            // launch chunks: segment-aligned ranges of at most `cap` quartets
+            bc.chunk_seg.push_back(bc.seg_lo);
+            int64_t start = 0;
+            for (int64_t sg = bc.seg_lo; sg < bc.seg_hi; ++sg) {
+                if (p->h_seg_off[sg + 1] - start > cap) {
+                    bc.chunk_seg.push_back(sg);
+                    start = p->h_seg_off[sg];
+                }
+            }
+            bc.chunk_seg.push_back(bc.seg_hi);
+            for (size_t k = 0; k + 1 < bc.chunk_seg.size(); ++k)
+                maxchunk = std::max(maxchunk, p->h_seg_off[bc.chunk_seg[k + 1]] - p->h_seg_off[bc.chunk_seg[k]]);
+            p->bclass.push_back(bc);
+        }
+    }
+    // ---- output ring: every quartet is written; the ring keeps the last ------
+    int64_t total_eri = 0;
+    for (auto& bc : p->bclass) total_eri += bc.n_quartets * (int64_t)tab[bc.cid].n_eriq;
+    const int64_t per_eri = p->code_bytes > 0 ? p->code_bytes : 8;
+    const double frac = (o->ring_bytes > 0 && total_eri * per_eri > o->ring_bytes)
+                            ? (double)o->ring_bytes / (double)(total_eri * per_eri) : 1.0;
+    for (auto& bc : p->bclass) {
+        int64_t r = (int64_t)std::floor(frac * (double)bc.n_quartets);
+        r = std::min<int64_t>(bc.n_quartets, std::max<int64_t>(r, 1));
+        bc.ring = r;
+        p->class_ring[bc.cid] = r;
+    }
+    p->class_qoff[0] = 0;
+    p->class_eoff[0] = 0;
+    for (int c = 0; c < 256; ++c) {
+        p->class_qoff[c + 1] = p->class_qoff[c] + p->class_ring[c];
+        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_ring[c] * (int64_t)tab[c].n_eriq;
+        p->n_quartets += p->class_count[c];
+        p->n_eri += p->class_count[c] * (int64_t)tab[c].n_eriq;
+    }
+    ERI_TRY(upload(p, (void**)&p->d_pairs, p->h_pairs.empty() ? nullptr : p->h_pairs.data(),
+                   p->h_pairs.size() * sizeof(eri_shell_pair)));
+    ERI_TRY(upload(p, (void**)&p->d_prims, prims.empty() ? nullptr : prims.data(), prims.size() * sizeof(eri_prim_pair)));
+    ERI_TRY(upload(p, (void**)&p->d_seg_off, p->h_seg_off.empty() ? nullptr : p->h_seg_off.data(),
+                   p->h_seg_off.size() * sizeof(int64_t)));
+    ERI_TRY(upload(p, (void**)&p->d_seg_p1, p->h_seg_p1.empty() ? nullptr : p->h_seg_p1.data(),
+                   p->h_seg_p1.size() * sizeof(int32_t)));
+    ERI_TRY(upload(p, (void**)&p->d_items, nullptr, (size_t)maxchunk * sizeof(eri_item)));
+    return ERI_OK;
 }
 
 extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* L, const int32_t* K,
@@ -106,21 +565,20 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
 {
     if (!out || !opts || n_shells < 0 || n_quartets < 0) return ERI_EINVAL;
     *out = nullptr;
-    if (n_shells > 0 && (!L || !K || !xyz || !prim_off || !exps || !coefs)) return ERI_EINVAL;
-    if (n_quartets > 0 && !quartets) return ERI_EINVAL;
-    if (n_shells > INT32_MAX) return ERI_EUNSUPPORTED;
+    const shell_set s{n_shells, L, K, xyz, prim_off, exps, coefs};
+    int rc = check_shells(s);
+    if (rc) return rc;
     if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED) return ERI_EUNSUPPORTED;
     if (opts->bits != 0 && (opts->bits < 2 || opts->bits > 32)) return ERI_EUNSUPPORTED;
-    for (int64_t s = 0; s < n_shells; ++s) {
-        if (L[s] < 0 || L[s] > ERI_MAX_L || K[s] < 1 || K[s] > ERI_MAX_K) return ERI_EUNSUPPORTED;
-        if (prim_off[s] < 0) return ERI_EINVAL;
-        for (int k = 0; k < K[s]; ++k)
-            if (!(exps[prim_off[s] + k] > 0.0)) return ERI_EINVAL;
+    if (!(opts->schwarz_threshold >= 0.0) || opts->ring_bytes < 0 || opts->chunk_quartets < 0) return ERI_EINVAL;
+    const bool batched = (opts->flags & ERI_PLAN_ALL_QUARTETS) != 0;
+    if (batched) {
+        if (quartets || n_quartets) return ERI_EINVAL;
+    } else {
+        if (n_quartets > 0 && !quartets) return ERI_EINVAL;
+        for (int64_t i = 0; i < 4 * n_quartets; ++i)
+            if (quartets[i] < 0 || quartets[i] >= n_shells) return ERI_EINVAL;
     }
-    for (int64_t i = 0; i < 4 * n_quartets; ++i)
-        if (quartets[i] < 0 || quartets[i] >= n_shells) return ERI_EINVAL;
-
-    const eri_kernel_info* tab = kernel_table(opts->precision);
     eri_plan* p = new (std::nothrow) eri_plan();
     if (!p) return ERI_ENOMEM;
     p->device = opts->device;
@@ -131,181 +589,23 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
         p->qmax = (double)((((int64_t)1) << (opts->bits - 1)) - 1);
         p->cn = 1.0 / p->qmax;
     }
-    p->n_quartets = n_quartets;
-
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != p->device) e = hipSetDevice(p->device);
+    if (e != hipSuccess) {
+        g_last_hip = (int)e;
+        delete p;
+        return ERI_EHIP;
+    }
     try {
-        // ---- class, orientation and shell pairs of every quartet --------------
-        std::vector<int32_t> cls(n_quartets);
-        std::vector<uint64_t> keys(2 * n_quartets);
-        bool bad_class = false;
-        for (int64_t t = 0; t < n_quartets; ++t) {
-            const int32_t* q = quartets + 4 * t;
-            const int c = L[q[0]] * 64 + L[q[1]] * 16 + L[q[2]] * 4 + L[q[3]];
-            if (!tab[c].fn) bad_class = true;
-            cls[t] = c;
-        }
-        if (bad_class) { plan_free(p); return ERI_EUNSUPPORTED; }
-        // A pair of equal angular momenta may go either way round; the VRR is
-        // put on the centre that keeps max_ij K_ij (1 + |P_ij - A|)^(2L) small,
-        // i.e. where the Gaussian products sit, so the HRR does not amplify.
-        auto vrr_score = [&](int32_t a, int32_t b) {
-            const double* A = xyz + 3 * (int64_t)a;
-            const double* B = xyz + 3 * (int64_t)b;
-            const double r2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
-            const double r = std::sqrt(r2);
-            double best = 0.0;
-            for (int i = 0; i < K[a]; ++i)
-                for (int j = 0; j < K[b]; ++j) {
-                    const double al = exps[prim_off[a] + i], be = exps[prim_off[b] + j], pe = al + be;
-                    const double s = std::exp(-al * be / pe * r2) * std::pow(1.0 + be / pe * r, 2 * L[a]);
-                    best = std::max(best, s);
-                }
-            return best;
-        };
-        std::vector<uint8_t> swp(n_quartets, 0);
-        parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
-            for (int64_t t = lo; t < hi; ++t) {
-                const int32_t* q = quartets + 4 * t;
-                const int pm = tab[cls[t]].perm;
-                int32_t ba = q[pm & 3], bb = q[(pm >> 2) & 3];
-                int32_t ka = q[(pm >> 4) & 3], kb = q[(pm >> 6) & 3];
-                uint8_t f = 0;
-                if (ba != bb && L[ba] == L[bb] && vrr_score(bb, ba) < vrr_score(ba, bb)) { std::swap(ba, bb); f |= 1; }
-                if (ka != kb && L[ka] == L[kb] && vrr_score(kb, ka) < vrr_score(ka, kb)) { std::swap(ka, kb); f |= 2; }
-                swp[t] = f;
-                keys[2 * t] = ((uint64_t)(uint32_t)ba << 32) | (uint32_t)bb;
-                keys[2 * t + 1] = ((uint64_t)(uint32_t)ka << 32) | (uint32_t)kb;
-            }
-        });
-        std::vector<uint64_t> uniq(keys);
-        std::sort(uniq.begin(), uniq.end());
-        uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
-        const int64_t npair = (int64_t)uniq.size();
-        if (npair > INT32_MAX) { plan_free(p); return ERI_EUNSUPPORTED; }
-        std::vector<eri_shell_pair> pairs(npair);
-        int64_t nprim = 0;
-        for (int64_t i = 0; i < npair; ++i) {
-            const int32_t sa = (int32_t)(uniq[i] >> 32), sb = (int32_t)(uniq[i] & 0xffffffffu);
-            eri_shell_pair& sp = pairs[i];
-            for (int x = 0; x < 3; ++x) sp.AB[x] = xyz[3 * (int64_t)sa + x] - xyz[3 * (int64_t)sb + x];
-            sp.prim_off = nprim;
-            sp.nprim = K[sa] * K[sb];
-            sp.kb = K[sb];
-            sp.sa = sa;
-            sp.sb = sb;
-            sp.pad[0] = sp.pad[1] = 0;
-            nprim += sp.nprim;
-        }
-        // c_k N(alpha_k, L) of every primitive of every shell
-        std::vector<int64_t> first(n_shells + 1, 0);
-        for (int64_t sh = 0; sh < n_shells; ++sh) first[sh + 1] = first[sh] + K[sh];
-        std::vector<double> cnorm(first[n_shells]);
-        parallel_for(n_shells, [&](int64_t lo, int64_t hi) {
-            for (int64_t sh = lo; sh < hi; ++sh)
-                for (int k = 0; k < K[sh]; ++k)
-                    cnorm[first[sh] + k] = coefs[prim_off[sh] + k] * norm_axis(exps[prim_off[sh] + k], L[sh]);
-        });
-        std::vector<eri_prim_pair> prims(nprim);
-        parallel_for(npair, [&](int64_t lo, int64_t hi) {
-            for (int64_t i = lo; i < hi; ++i) {
-                const eri_shell_pair& sp = pairs[i];
-                const int32_t sa = sp.sa, sb = sp.sb;
-                const double* A = xyz + 3 * (int64_t)sa;
-                const double* B = xyz + 3 * (int64_t)sb;
-                const double ab2 = sp.AB[0] * sp.AB[0] + sp.AB[1] * sp.AB[1] + sp.AB[2] * sp.AB[2];
-                for (int ia = 0; ia < K[sa]; ++ia)
-                    for (int ib = 0; ib < K[sb]; ++ib) {
-                        const double al = exps[prim_off[sa] + ia], be = exps[prim_off[sb] + ib];
-                        eri_prim_pair& pp = prims[sp.prim_off + ia * K[sb] + ib];
-                        const double pe = al + be;
-                        pp.p = pe;
-                        pp.hp = 0.5 / pe;
-                        const double kab = cnorm[first[sa] + ia] * cnorm[first[sb] + ib] *
-                                           std::exp(-al * be / pe * ab2);
-                        pp.kp = kab / pe;
-                        for (int x = 0; x < 3; ++x) {
-                            pp.P[x] = (al * A[x] + be * B[x]) / pe;
-                            pp.PA[x] = pp.P[x] - A[x];
-                        }
-                        pp.alpha = al;
-                        pp.beta = be;
-                        pp.pad = 0.0;
-                    }
-            }
-        });
-        // ---- plan order: class, then bra and ket primitive counts -------------
-        std::vector<int32_t> bra(n_quartets), ket(n_quartets);
-        parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
-            for (int64_t t = lo; t < hi; ++t) {
-                bra[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[2 * t]) - uniq.begin());
-                ket[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[2 * t + 1]) - uniq.begin());
-            }
-        });
-        std::vector<uint64_t>().swap(uniq);
-        std::vector<uint64_t>().swap(keys);
-        // sort key: class (8 bits), bra and ket primitive counts (9 bits each),
-        // then the user index (32 bits): a plain sort is stable in user order
-        std::vector<uint64_t> order(n_quartets);
-        parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
-            for (int64_t t = lo; t < hi; ++t) {
-                const uint64_t nb = (uint64_t)std::min(pairs[bra[t]].nprim, 511);
-                const uint64_t nk = (uint64_t)std::min(pairs[ket[t]].nprim, 511);
-                order[t] = ((uint64_t)cls[t] << 50) | (nb << 41) | (nk << 32) | (uint64_t)t;
-            }
-        });
-        if (n_quartets > (int64_t)UINT32_MAX) { plan_free(p); return ERI_EUNSUPPORTED; }
-        std::sort(order.begin(), order.end());
-        std::vector<eri_item> items(n_quartets);
-        p->pos.assign(n_quartets, 0);
-        p->eri_off.assign(n_quartets, 0);
-        for (int64_t j = 0; j < n_quartets; ++j) {
-            const int64_t t = (int64_t)(order[j] & 0xffffffffu);
-            items[j].bra = (int32_t)((uint32_t)bra[t] | ((swp[t] & 1) ? 0x80000000u : 0u));
-            items[j].ket = (int32_t)((uint32_t)ket[t] | ((swp[t] & 2) ? 0x80000000u : 0u));
-            p->pos[t] = j;
-            p->class_count[cls[t]] += 1;
-            const int64_t npq = (int64_t)pairs[bra[t]].nprim * pairs[ket[t]].nprim;
-            p->n_prim_quartets += npq;
-            p->class_flops[cls[t]] += (double)npq * tab[cls[t]].flops_pq + (double)tab[cls[t]].flops_q;
-        }
-        p->class_qoff[0] = 0;
-        p->class_eoff[0] = 0;
-        for (int c = 0; c < 256; ++c) {
-            p->class_qoff[c + 1] = p->class_qoff[c] + p->class_count[c];
-            p->class_eoff[c + 1] = p->class_eoff[c] + p->class_count[c] * (int64_t)tab[c].n_eriq;
-        }
-        p->n_eri = p->class_eoff[256];
-        for (int64_t t = 0; t < n_quartets; ++t) {
-            const int c = cls[t];
-            p->eri_off[t] = p->class_eoff[c] + (p->pos[t] - p->class_qoff[c]) * (int64_t)tab[c].n_eriq;
-        }
-        p->n_pairs = npair;
-        p->n_prims = nprim;
-
-        // ---- upload -----------------------------------------------------------
-        int cur = 0;
-        ERI_HIP_TRY(hipGetDevice(&cur));
-        if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
-        int rc = ERI_OK;
-        auto up = [&](void** dst, const void* src, size_t bytes) -> int {
-            if (bytes == 0) bytes = 64;
-            hipError_t e = hipMalloc(dst, bytes);
-            if (e != hipSuccess) { g_last_hip = (int)e; return e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP; }
-            p->device_bytes += (int64_t)bytes;
-            if (src) {
-                e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
-                if (e != hipSuccess) { g_last_hip = (int)e; return ERI_EHIP; }
-            }
-            return ERI_OK;
-        };
-        if (rc == ERI_OK) rc = up((void**)&p->d_pairs, pairs.empty() ? nullptr : pairs.data(), pairs.size() * sizeof(eri_shell_pair));
-        if (rc == ERI_OK) rc = up((void**)&p->d_prims, prims.empty() ? nullptr : prims.data(), prims.size() * sizeof(eri_prim_pair));
-        if (rc == ERI_OK) rc = up((void**)&p->d_items, items.empty() ? nullptr : items.data(), items.size() * sizeof(eri_item));
-        if (cur != p->device) (void)hipSetDevice(cur);
-        if (rc != ERI_OK) { plan_free(p); return rc; }
+        rc = batched ? create_batched(p, s, opts) : create_explicit(p, s, quartets, n_quartets);
     } catch (const std::bad_alloc&) {
+        rc = ERI_ENOMEM;
+    }
+    if (cur != p->device) (void)hipSetDevice(cur);
+    if (rc != ERI_OK) {
         plan_free(p);
-        return ERI_ENOMEM;
+        return rc;
     }
     *out = p;
     return ERI_OK;
@@ -323,8 +623,10 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
     info->device_bytes = p->device_bytes;
     info->code_bytes = p->code_bytes;
     info->bits = p->bits;
+    info->batched = p->batched ? 1 : 0;
     for (int c = 0; c < 256; ++c) {
         info->class_quartets[c] = p->class_count[c];
+        info->class_ring[c] = p->class_ring[c];
         info->class_flops[c] = p->class_flops[c];
     }
     for (int c = 0; c <= 256; ++c) {
@@ -337,19 +639,43 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
 extern "C" int eri_plan_layout(const eri_plan* p, int64_t* pos, int64_t* eri_off)
 {
     if (!p || (!pos && !eri_off)) return ERI_EINVAL;
+    if (p->batched) return ERI_ESTATE;
     if (pos) std::copy(p->pos.begin(), p->pos.end(), pos);
     if (eri_off) std::copy(p->eri_off.begin(), p->eri_off.end(), eri_off);
     return ERI_OK;
 }
 
-static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
+extern "C" int eri_plan_quartets(const eri_plan* p, int32_t class_id, int64_t first, int64_t count, int32_t* out)
 {
-    const int64_t n = p->class_count[c];
-    if (n == 0) return ERI_OK;
-    const eri_kernel_info& ki = kernel_table(p->precision)[c];
-    eri_class_args a;
-    a.items = p->d_items + p->class_qoff[c];
-    a.n_items = n;
+    if (!p || !out || class_id < 0 || class_id > 255 || first < 0 || count < 0) return ERI_EINVAL;
+    if (first + count > p->class_count[class_id]) return ERI_EINVAL;
+    if (count == 0) return ERI_OK;
+    if (!p->batched) {
+        const int32_t* q = p->quartets.data() + 4 * (p->class_qoff[class_id] + first);
+        std::copy(q, q + 4 * count, out);
+        return ERI_OK;
+    }
+    const eri_batch_class* bc = nullptr;
+    for (auto& b : p->bclass)
+        if (b.cid == class_id) bc = &b;
+    if (!bc) return ERI_EINVAL;
+    // segment holding quartet `first`
+    int64_t sg = (int64_t)(std::upper_bound(p->h_seg_off.begin() + bc->seg_lo, p->h_seg_off.begin() + bc->seg_hi, first) -
+                           p->h_seg_off.begin()) - 1;
+    for (int64_t t = first; t < first + count; ++t) {
+        while (t >= p->h_seg_off[sg + 1]) ++sg;
+        const int32_t p1 = p->h_seg_p1[sg];
+        const int64_t p2 = bc->ket_lo + (t - p->h_seg_off[sg]);
+        const eri_shell_pair& a = p->h_pairs[p1];
+        const eri_shell_pair& b = p->h_pairs[p2];
+        int32_t* o = out + 4 * (t - first);
+        o[0] = a.sa; o[1] = a.sb; o[2] = b.sa; o[3] = b.sb;
+    }
+    return ERI_OK;
+}
+
+static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, void* out_codes, double* out_scales)
+{
     a.pairs = p->d_pairs;
     a.prims = p->d_prims;
     a.out_eri = out_eri ? out_eri + p->class_eoff[c] : nullptr;
@@ -359,10 +685,48 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
     a.qmax = p->qmax;
     a.code_bytes = p->code_bytes;
     a.pad = 0;
-    const int64_t grid = (n + ki.per_block - 1) / ki.per_block;
+    a.ring = p->class_ring[c];
+    a.qbase = 0;
+}
+
+static int launch_items(const eri_kernel_info& ki, eri_class_args& a, hipStream_t st)
+{
+    const int64_t grid = (a.n_items + ki.per_block - 1) / ki.per_block;
+    if (grid == 0) return ERI_OK;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     void* args[] = {&a};
     ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, st));
+    return ERI_OK;
+}
+
+static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
+{
+    const int64_t n = p->class_count[c];
+    if (n == 0) return ERI_OK;
+    const eri_kernel_info& ki = kernel_table(p->precision)[c];
+    eri_class_args a;
+    fill_args(p, c, a, out_eri, out_codes, out_scales);
+    if (!p->batched) {
+        a.items = p->d_items + p->class_qoff[c];
+        a.n_items = n;
+        return launch_items(ki, a, st);
+    }
+    const eri_batch_class* bc = nullptr;
+    for (auto& b : p->bclass)
+        if (b.cid == c) bc = &b;
+    if (!bc) return ERI_OK;
+    for (size_t k = 0; k + 1 < bc->chunk_seg.size(); ++k) {
+        const int64_t s0 = bc->chunk_seg[k], s1 = bc->chunk_seg[k + 1];
+        if (s1 <= s0) continue;
+        const int64_t q0 = p->h_seg_off[s0], q1 = p->h_seg_off[s1];
+        hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, st, p->d_seg_off, p->d_seg_p1,
+                           s0, bc->ket_lo, q0, bc->swap ? 1 : 0, p->d_items);
+        ERI_HIP_TRY(hipGetLastError());
+        a.items = p->d_items;
+        a.n_items = q1 - q0;
+        a.qbase = q0;
+        ERI_TRY(launch_items(ki, a, st));
+    }
     return ERI_OK;
 }
 
@@ -374,6 +738,47 @@ static int compute_check(eri_plan* p, double* out_eri, void* out_codes, double* 
     return ERI_OK;
 }
 
+static int launch_all(eri_plan* p, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
+{
+    for (int c = 0; c < 256; ++c) ERI_TRY(launch_class(p, c, st, out_eri, out_codes, out_scales));
+    return ERI_OK;
+}
+
+// Batched plans: every launch (item expansion + class kernels, all chunks) is
+// captured once into a graph, then replayed as one launch per call.
+static int graph_launch(eri_plan* p, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
+{
+    const void* key[4] = {out_eri, out_codes, out_scales, nullptr};
+    if (!p->graph || std::memcmp(key, p->graph_key, sizeof(key)) != 0) {
+        if (p->graph) {
+            (void)hipGraphExecDestroy(p->graph);
+            p->graph = nullptr;
+        }
+        hipStream_t cap = nullptr;
+        ERI_HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        int rc = ERI_OK;
+        hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = launch_all(p, cap, out_eri, out_codes, out_scales);
+            hipError_t e2 = hipStreamEndCapture(cap, &g);
+            if (rc == ERI_OK) e = e2;
+        }
+        if (e == hipSuccess && rc == ERI_OK) e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cap);
+        if (rc != ERI_OK) return rc;
+        if (e != hipSuccess) {
+            p->graph = nullptr;
+            g_last_hip = (int)e;
+            return ERI_EHIP;
+        }
+        std::memcpy(p->graph_key, key, sizeof(key));
+    }
+    ERI_HIP_TRY(hipGraphLaunch(p->graph, st));
+    return ERI_OK;
+}
+
 extern "C" int eri_compute(eri_plan* p, void* stream, double* out_eri, void* out_codes, double* out_scales)
 {
     int rc = compute_check(p, out_eri, out_codes, out_scales);
@@ -381,8 +786,8 @@ extern "C" int eri_compute(eri_plan* p, void* stream, double* out_eri, void* out
     int cur = 0;
     ERI_HIP_TRY(hipGetDevice(&cur));
     if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
-    for (int c = 0; c < 256 && rc == ERI_OK; ++c)
-        rc = launch_class(p, c, (hipStream_t)stream, out_eri, out_codes, out_scales);
+    hipStream_t st = (hipStream_t)stream;
+    rc = p->batched ? graph_launch(p, st, out_eri, out_codes, out_scales) : launch_all(p, st, out_eri, out_codes, out_scales);
     if (cur != p->device) (void)hipSetDevice(cur);
     return rc;
 }

@@ -46,4 +46,6 @@ struct eri_class_args {
     double qmax;                    // 2^(bits-1) - 1
     int32_t code_bytes;             // 1, 2 or 4
     int32_t pad;
+    int64_t ring;                   // output slots of the class: quartet q lands in slot q mod ring
+    int64_t qbase;                  // class index of this launch's first quartet
 };

@@ -36,9 +36,14 @@ class EriError(RuntimeError):
         self.status = status
 
 
+ERI_PLAN_ALL_QUARTETS = 1
+
+
 class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("bits", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("schwarz_threshold", ctypes.c_double), ("ring_bytes", ctypes.c_int64),
+                ("chunk_quartets", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -46,7 +51,9 @@ class PlanInfo(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64), ("n_prim_pairs", ctypes.c_int64),
                 ("n_prim_quartets", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
                 ("code_bytes", ctypes.c_int32), ("bits", ctypes.c_int32),
-                ("class_quartets", ctypes.c_int64 * 256), ("class_eri_off", ctypes.c_int64 * 257),
+                ("batched", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("class_quartets", ctypes.c_int64 * 256), ("class_ring", ctypes.c_int64 * 256),
+                ("class_eri_off", ctypes.c_int64 * 257),
                 ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256)]
 
 
@@ -68,6 +75,7 @@ def load():
                                     _f64p, _f64p, _i32p, ctypes.c_int64, ctypes.POINTER(PlanOpts)]
     lib.eri_plan_info_get.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
     lib.eri_plan_layout.argtypes = [_vp, _i64p, _i64p]
+    lib.eri_plan_quartets.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _i32p]
     lib.eri_compute.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.eri_compute_class.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
     lib.eri_compress.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
@@ -112,17 +120,25 @@ def _stream(stream):
 
 
 class Plan:
-    """A plan over the quartets of a shell set (see include/eri.h)."""
+    """A plan over the quartets of a shell set (see include/eri.h).
 
-    def __init__(self, shells, quartets, precision="fp64", bits=16, device=0):
+    quartets=None plans every unique quartet whose Schwarz bound reaches
+    `schwarz`; its outputs form per-class rings bounded by `ring_bytes`."""
+
+    def __init__(self, shells, quartets, precision="fp64", bits=16, device=0, schwarz=1e-10,
+                 ring_bytes=0, chunk_quartets=0):
         lib = load()
         self.shells = shells
-        q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+        self.batched = quartets is None
+        q = np.zeros((0, 4), dtype=np.int32) if self.batched else \
+            np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
         self.quartets = q
         self.precision = precision
         self.bits = int(bits)
         self.device = int(device)
-        opts = PlanOpts(PRECISIONS[precision], self.bits, self.device, 0)
+        opts = PlanOpts(PRECISIONS[precision], self.bits, self.device,
+                        ERI_PLAN_ALL_QUARTETS if self.batched else 0, float(schwarz),
+                        int(ring_bytes), int(chunk_quartets))
         h = _vp()
         L = np.ascontiguousarray(shells["L"], dtype=np.int32)
         K = np.ascontiguousarray(shells["K"], dtype=np.int32)
@@ -133,9 +149,12 @@ class Plan:
         if len(ex) == 0:
             ex = np.zeros(1)
             co = np.zeros(1)
-        rc = lib.eri_plan_create(ctypes.byref(h), len(L), L, K, xyz, off, ex, co,
-                                 q.reshape(-1) if len(q) else np.zeros(4, dtype=np.int32), len(q),
-                                 ctypes.byref(opts))
+        qarg = None if self.batched else (q.reshape(-1) if len(q) else np.zeros(4, dtype=np.int32))
+        if qarg is None:
+            lib.eri_plan_create.argtypes = lib.eri_plan_create.argtypes[:8] + [_vp] + lib.eri_plan_create.argtypes[9:]
+        else:
+            lib.eri_plan_create.argtypes = lib.eri_plan_create.argtypes[:8] + [_i32p] + lib.eri_plan_create.argtypes[9:]
+        rc = lib.eri_plan_create(ctypes.byref(h), len(L), L, K, xyz, off, ex, co, qarg, len(q), ctypes.byref(opts))
         _check(rc, "eri_plan_create")
         self._h = h
         info = PlanInfo()
@@ -148,6 +167,7 @@ class Plan:
         self.device_bytes = info.device_bytes
         self.code_bytes = info.code_bytes
         self.class_quartets = np.array(info.class_quartets[:], dtype=np.int64)
+        self.class_ring = np.array(info.class_ring[:], dtype=np.int64)
         self.class_eri_off = np.array(info.class_eri_off[:], dtype=np.int64)
         self.class_quartet_off = np.array(info.class_quartet_off[:], dtype=np.int64)
         self.class_flops = np.array(info.class_flops[:], dtype=np.float64)
@@ -164,15 +184,33 @@ class Plan:
             self._pos, self._eri_off = pos[:n], eoff[:n]
         return self._pos, self._eri_off
 
+    @property
+    def out_values(self):
+        """Length of the value/code arrays (plan order, rings included)."""
+        return int(self.class_eri_off[256])
+
+    @property
+    def out_blocks(self):
+        """Length of the scale array."""
+        return int(self.class_quartet_off[256])
+
     def alloc(self, eri=True, codes=True):
         import torch
         dev = torch.device("cuda", self.device)
-        out_eri = torch.empty(max(int(self.n_eri), 1), dtype=torch.float64, device=dev) if eri else None
+        out_eri = torch.empty(max(self.out_values, 1), dtype=torch.float64, device=dev) if eri else None
         out_codes = out_scales = None
         if codes and self.bits > 0:
-            out_codes = torch.empty(max(int(self.n_eri), 1), dtype=code_dtype(self.bits), device=dev)
-            out_scales = torch.empty(max(int(self.n_quartets), 1), dtype=torch.float64, device=dev)
+            out_codes = torch.empty(max(self.out_values, 1), dtype=code_dtype(self.bits), device=dev)
+            out_scales = torch.empty(max(self.out_blocks, 1), dtype=torch.float64, device=dev)
         return out_eri, out_codes, out_scales
+
+    def class_quartet_list(self, cid, first=0, count=None):
+        """Shell quartets of class `cid` in output order (int32 [count, 4])."""
+        n = int(self.class_quartets[cid])
+        count = n - first if count is None else count
+        out = np.zeros(max(4 * count, 4), dtype=np.int32)
+        _check(load().eri_plan_quartets(self._h, int(cid), int(first), int(count), out), "eri_plan_quartets")
+        return out[: 4 * count].reshape(-1, 4)
 
     def compute(self, out_eri=None, out_codes=None, out_scales=None, stream=None):
         _check(load().eri_compute(self._h, _stream(stream), _ptr(out_eri), _ptr(out_codes), _ptr(out_scales)),
