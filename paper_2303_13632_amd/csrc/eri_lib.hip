@@ -167,7 +167,8 @@ struct eri_batch_class {
     int64_t seg_lo = 0, seg_hi = 0; // range in the plan's segment arrays
     int64_t ket_lo = 0;             // first ket pair (global index) of the ket class
     int64_t ring = 0;               // output slots
-    std::vector<int64_t> chunk_seg; // segment boundaries of the launch chunks
+    int64_t chunk = 0;              // quartets per launch (<= ring: no two quartets of
+                                    // one launch share a ring slot)
 };
 
 struct eri_plan {
@@ -354,18 +355,20 @@ static int create_explicit(eri_plan* p, const shell_set& s, const int32_t* quart
 // ---------------------------------------------------------------------------
 // Batched plans: all unique Schwarz-screened quartets of a shell set
 // ---------------------------------------------------------------------------
-// Writes the items (computed bra, computed ket) of segments [seg_lo, seg_lo +
-// gridDim.x) of one class; seg_off holds quartet offsets within the class.
+// Writes the items (computed bra, computed ket) of class quartets [q_lo, q_hi)
+// that fall in segments [seg_lo, seg_lo + gridDim.x); seg_off holds quartet
+// offsets within the class.
 __global__ __launch_bounds__(256) void eri_expand_kernel(const int64_t* __restrict__ seg_off,
                                                          const int32_t* __restrict__ seg_p1, int64_t seg_lo,
-                                                         int64_t ket_lo, int64_t q_lo, int swap,
+                                                         int64_t ket_lo, int64_t q_lo, int64_t q_hi, int swap,
                                                          eri_item* __restrict__ items)
 {
     const int64_t s = seg_lo + blockIdx.x;
-    const int64_t beg = seg_off[s], end = seg_off[s + 1];
+    const int64_t sb = seg_off[s], se = seg_off[s + 1];
+    const int64_t beg = sb > q_lo ? sb : q_lo, end = se < q_hi ? se : q_hi;
     const int32_t p1 = seg_p1[s];
     for (int64_t t = beg + threadIdx.x; t < end; t += 256) {
-        const int32_t p2 = (int32_t)(ket_lo + (t - beg));
+        const int32_t p2 = (int32_t)(ket_lo + (t - sb));
         eri_item it;
         it.bra = swap ? p2 : p1;
         it.ket = swap ? p1 : p2;
@@ -496,7 +499,6 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
                 int64_t n = lo - k0;
                 if (cb == ck) n = std::min(n, b - b0 + 1);
                 if (n <= 0) continue;
-                if (n > cap) return ERI_EUNSUPPORTED;
                 p->h_seg_off.push_back(q);
                 p->h_seg_p1.push_back((int32_t)b);
                 q += n;
@@ -512,18 +514,6 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
             bc.n_quartets = q;
             p->class_count[cid] = q;
             p->class_flops[cid] = flops;
-            // launch chunks: segment-aligned ranges of at most `cap` quartets
-            bc.chunk_seg.push_back(bc.seg_lo);
-            int64_t start = 0;
-            for (int64_t sg = bc.seg_lo; sg < bc.seg_hi; ++sg) {
-                if (p->h_seg_off[sg + 1] - start > cap) {
-                    bc.chunk_seg.push_back(sg);
-                    start = p->h_seg_off[sg];
-                }
-            }
-            bc.chunk_seg.push_back(bc.seg_hi);
-            for (size_t k = 0; k + 1 < bc.chunk_seg.size(); ++k)
-                maxchunk = std::max(maxchunk, p->h_seg_off[bc.chunk_seg[k + 1]] - p->h_seg_off[bc.chunk_seg[k]]);
             p->bclass.push_back(bc);
         }
     }
@@ -537,6 +527,8 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
         int64_t r = (int64_t)std::floor(frac * (double)bc.n_quartets);
         r = std::min<int64_t>(bc.n_quartets, std::max<int64_t>(r, 1));
         bc.ring = r;
+        bc.chunk = std::min(cap, r);
+        maxchunk = std::max(maxchunk, bc.chunk);
         p->class_ring[bc.cid] = r;
     }
     p->class_qoff[0] = 0;
@@ -715,12 +707,15 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
     for (auto& b : p->bclass)
         if (b.cid == c) bc = &b;
     if (!bc) return ERI_OK;
-    for (size_t k = 0; k + 1 < bc->chunk_seg.size(); ++k) {
-        const int64_t s0 = bc->chunk_seg[k], s1 = bc->chunk_seg[k + 1];
-        if (s1 <= s0) continue;
-        const int64_t q0 = p->h_seg_off[s0], q1 = p->h_seg_off[s1];
+    const auto sbeg = p->h_seg_off.begin();
+    for (int64_t q0 = 0; q0 < bc->n_quartets; q0 += bc->chunk) {
+        const int64_t q1 = std::min(bc->n_quartets, q0 + bc->chunk);
+        // segments overlapping [q0, q1)
+        const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q0) - sbeg) - 1;
+        const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q1) - sbeg);
+        if (s1 - s0 > INT32_MAX) return ERI_EUNSUPPORTED;
         hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, st, p->d_seg_off, p->d_seg_p1,
-                           s0, bc->ket_lo, q0, bc->swap ? 1 : 0, p->d_items);
+                           s0, bc->ket_lo, q0, q1, bc->swap ? 1 : 0, p->d_items);
         ERI_HIP_TRY(hipGetLastError());
         a.items = p->d_items;
         a.n_items = q1 - q0;
