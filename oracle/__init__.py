@@ -15,6 +15,7 @@ from .oracle import (  # noqa: F401
     primitive_block,
     compress,
     decompress,
+    gradient,
     ncart,
     components,
 )

@@ -41,6 +41,9 @@
  *     clamped to +-(2^(n-1)-1); b_max = 0 gives eps = 0 and all codes 0; when
  *     eps is so small (subnormal) that 1/eps overflows, q = ANINT(x/eps).
  *     Built with -ffp-contract=off so every operation is one IEEE rounding.
+ *   - Gradients (not in the paper; the adjoint of the ERIs): the same Rys
+ *     routine applied to the differentiated Gaussians, all four centres
+ *     differentiated explicitly, exponents per primitive, coefficients fixed.
  *
  * Two instantiations of the quadrature core are built: one in double (roots
  * and weights rounded to double), and one entirely in __float128 that serves
@@ -446,5 +449,156 @@ int oracle_decompress(int64_t n_blocks, const int64_t *off, const int32_t *codes
     for (int64_t b = 0; b < n_blocks; ++b)
         for (int64_t i = off[b]; i < off[b + 1]; ++i)
             out[i] = (double)codes[i] * eps[b];
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Analytic gradient of L = sum_q deg_q sum_(abcd) Gbar_q(abcd) (ab|cd)_q     */
+/* with respect to every shell centre and every primitive exponent.           */
+/* Differentiated Gaussians (unnormalised x^a exp(-alpha r^2) per axis):      */
+/*   d/dA_x g_a = 2 alpha g_(a+1_x) - a_x g_(a-1_x);                          */
+/*   d/dalpha [N(alpha,L) g_a] = N [(3/4 + L/2)/alpha g_a - sum_x g_(a+2_x)]. */
+/* All four centres are differentiated explicitly.                           */
+/* Gbar comes either from `dl` (per-quartet values in the output layout of    */
+/* oracle_eri) or from a symmetric density D (nbf x nbf, shells' functions    */
+/* numbered in shell order): Gbar = D[mu nu] D[lam sig].                      */
+/* ------------------------------------------------------------------------- */
+static int comp_index(int lx, int ly, int lz)
+{
+    int L = lx + ly + lz;
+    return (L - lx) * (L - lx + 1) / 2 + (L - lx - ly);
+}
+
+int oracle_gradient(int64_t n_shells, const int32_t *shL, const int32_t *shK, const double *xyz,
+                    const int64_t *off, const double *exps, const double *coefs,
+                    int64_t n_quartets, const int32_t *quartets, const double *deg,
+                    const double *dl, const int64_t *dl_off, const double *dens, int64_t nbf,
+                    double *grad_xyz, double *grad_exp, double *energy, int n_threads)
+{
+    if (n_shells < 0 || n_quartets < 0) return -1;
+    if (check_shells(n_shells, shL, shK, 3)) return -2;
+    if (!dl && !dens) return -1;
+    if (n_shells == 0 || n_quartets == 0) {
+        if (energy) *energy = 0.0;
+        for (int64_t i = 0; i < 3 * n_shells; ++i) grad_xyz[i] = 0.0;
+        for (int64_t s = 0; s < n_shells; ++s)
+            for (int k = 0; k < shK[s]; ++k) grad_exp[off[s] + k] = 0.0;
+        return 0;
+    }
+    int64_t *bf = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_shells + 1));
+    bf[0] = 0;
+    for (int64_t s = 0; s < n_shells; ++s) bf[s + 1] = bf[s] + ncart(shL[s]);
+    if (dens && bf[n_shells] != nbf) { free(bf); return -3; }
+    int64_t nprim_total = off[n_shells - 1] + shK[n_shells - 1];
+    for (int64_t s = 0; s < n_shells; ++s)
+        if (off[s] + shK[s] > nprim_total) nprim_total = off[s] + shK[s];
+    double etot = 0.0;
+    int nt = n_threads > 0 ? n_threads : 1;
+    double *gx_all = (double *)calloc((size_t)nt * (size_t)(3 * n_shells), sizeof(double));
+    double *ge_all = (double *)calloc((size_t)nt * (size_t)nprim_total, sizeof(double));
+    double *e_all = (double *)calloc((size_t)nt, sizeof(double));
+    _Pragma("omp parallel for schedule(dynamic, 1) num_threads(nt)")
+    for (int64_t t = 0; t < n_quartets; ++t) {
+        int tid = 0;
+#ifdef _OPENMP
+        tid = omp_get_thread_num();
+#endif
+        double *gx = gx_all + (size_t)tid * (size_t)(3 * n_shells);
+        double *ge = ge_all + (size_t)tid * (size_t)nprim_total;
+        const int32_t *q = quartets + 4 * t;
+        int L[4], comps[4][64][3], nc[4];
+        double R[4][3];
+        for (int s = 0; s < 4; ++s) {
+            L[s] = shL[q[s]];
+            nc[s] = orc_components(L[s], comps[s]);
+            for (int x = 0; x < 3; ++x) R[s][x] = xyz[3 * (int64_t)q[s] + x];
+        }
+        const int n = nc[0] * nc[1] * nc[2] * nc[3];
+        double *G = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int ia = 0, o = 0; ia < nc[0]; ++ia)
+            for (int ib = 0; ib < nc[1]; ++ib)
+                for (int ic = 0; ic < nc[2]; ++ic)
+                    for (int id = 0; id < nc[3]; ++id, ++o) {
+                        if (dl) G[o] = deg[t] * dl[dl_off[t] + o];
+                        else G[o] = deg[t] * dens[(bf[q[0]] + ia) * nbf + bf[q[1]] + ib]
+                                             * dens[(bf[q[2]] + ic) * nbf + bf[q[3]] + id];
+                    }
+        double *work = (double *)malloc(ORC_WORK_ELEMS * sizeof(double));
+        /* blocks: base, and for each centre s: L+1, L-1, L+2 */
+        int nmax = 1;
+        for (int s = 0; s < 4; ++s) nmax *= ncart(L[s] + 2);
+        double *blk = (double *)malloc(sizeof(double) * (size_t)nmax);
+        double *base = (double *)malloc(sizeof(double) * (size_t)n);
+        for (int i = 0; i < shK[q[0]]; ++i)
+          for (int j = 0; j < shK[q[1]]; ++j)
+            for (int k = 0; k < shK[q[2]]; ++k)
+              for (int l = 0; l < shK[q[3]]; ++l) {
+                  const int pi[4] = {i, j, k, l};
+                  double ex[4], cn[4], scale = 1.0;
+                  for (int s = 0; s < 4; ++s) {
+                      ex[s] = exps[off[q[s]] + pi[s]];
+                      cn[s] = coefs[off[q[s]] + pi[s]] * (double)norm_quad((qreal)ex[s], L[s]);
+                      scale *= cn[s];
+                  }
+                  memset(base, 0, sizeof(double) * (size_t)n);
+                  rys_primitive_d(L, (const double(*)[3])R, ex, 1.0, base, work);
+                  double gb = 0.0;
+                  for (int o = 0; o < n; ++o) gb += G[o] * base[o];
+                  e_all[tid] += scale * gb;
+                  for (int s = 0; s < 4; ++s) {
+                      double dx[3] = {0, 0, 0}, dexp = (0.75 + 0.5 * L[s]) / ex[s] * gb;
+                      for (int shift = -1; shift <= 2; ++shift) {
+                          if (shift == 0 || L[s] + shift < 0) continue;
+                          int L2[4] = {L[0], L[1], L[2], L[3]};
+                          L2[s] += shift;
+                          int n2[4];
+                          for (int u = 0; u < 4; ++u) n2[u] = ncart(L2[u]);
+                          memset(blk, 0, sizeof(double) * (size_t)(n2[0] * n2[1] * n2[2] * n2[3]));
+                          rys_primitive_d(L2, (const double(*)[3])R, ex, 1.0, blk, work);
+                          int st[4] = {n2[1] * n2[2] * n2[3], n2[2] * n2[3], n2[3], 1};
+                          int stb[4] = {nc[1] * nc[2] * nc[3], nc[2] * nc[3], nc[3], 1};
+                          for (int o = 0; o < n; ++o) {
+                              if (G[o] == 0.0) continue;
+                              int rem = o, ci[4];
+                              for (int u = 0; u < 4; ++u) { ci[u] = rem / stb[u]; rem -= ci[u] * stb[u]; }
+                              int base_idx = 0;
+                              for (int u = 0; u < 4; ++u)
+                                  if (u != s) base_idx += ci[u] * st[u];
+                              const int *a = comps[s][ci[s]];
+                              for (int x = 0; x < 3; ++x) {
+                                  int c2[3] = {a[0], a[1], a[2]};
+                                  if (shift == 1) {
+                                      c2[x] += 1;
+                                      dx[x] += G[o] * 2.0 * ex[s] * blk[base_idx + comp_index(c2[0], c2[1], c2[2]) * st[s]];
+                                  } else if (shift == -1) {
+                                      if (a[x] == 0) continue;
+                                      c2[x] -= 1;
+                                      dx[x] -= G[o] * a[x] * blk[base_idx + comp_index(c2[0], c2[1], c2[2]) * st[s]];
+                                  } else {
+                                      c2[x] += 2;
+                                      dexp -= G[o] * blk[base_idx + comp_index(c2[0], c2[1], c2[2]) * st[s]];
+                                  }
+                              }
+                          }
+                      }
+                      for (int x = 0; x < 3; ++x) gx[3 * (int64_t)q[s] + x] += scale * dx[x];
+                      ge[off[q[s]] + pi[s]] += scale * dexp;
+                  }
+              }
+        free(base); free(blk); free(work); free(G);
+    }
+    for (int64_t i = 0; i < 3 * n_shells; ++i) {
+        double s = 0.0;
+        for (int tt = 0; tt < nt; ++tt) s += gx_all[(size_t)tt * (size_t)(3 * n_shells) + (size_t)i];
+        grad_xyz[i] = s;
+    }
+    for (int64_t i = 0; i < nprim_total; ++i) {
+        double s = 0.0;
+        for (int tt = 0; tt < nt; ++tt) s += ge_all[(size_t)tt * (size_t)nprim_total + (size_t)i];
+        grad_exp[i] = s;
+    }
+    for (int tt = 0; tt < nt; ++tt) etot += e_all[tt];
+    if (energy) *energy = etot;
+    free(gx_all); free(ge_all); free(e_all); free(bf);
     return 0;
 }

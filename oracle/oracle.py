@@ -57,6 +57,10 @@ def load():
     lib.oracle_primitive_block.argtypes = [_i32p, _f64p, _f64p, _f64p]
     lib.oracle_compress.argtypes = [ctypes.c_int, ctypes.c_int64, _i64p, _f64p, _i32p, _f64p]
     lib.oracle_decompress.argtypes = [ctypes.c_int64, _i64p, _i32p, _f64p, _f64p]
+    _vp = ctypes.c_void_p
+    lib.oracle_gradient.argtypes = [ctypes.c_int64, _i32p, _i32p, _f64p, _i64p, _f64p, _f64p,
+                                    ctypes.c_int64, _i32p, _f64p, _vp, _vp, _vp, ctypes.c_int64,
+                                    _f64p, _f64p, _f64p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -163,3 +167,50 @@ def decompress(codes, eps, block_off):
     if load().oracle_decompress(len(block_off) - 1, block_off, codes, eps, out) != 0:
         raise ValueError("oracle_decompress: bad arguments")
     return out
+
+
+def gradient(shells, quartets, weights=None, dl=None, density=None, n_threads=None):
+    """Analytic gradient of  L = sum_t w_t sum_(abcd) Gbar_t(abcd) (ab|cd)_t
+    with Gbar = dl (values in the layout of eri(), i.e. quartet t at its
+    offset) or Gbar = D[mu nu] D[lam sig] from a symmetric density over the
+    basis functions numbered shell by shell.  Returns (L, dL/dxyz [n, 3],
+    dL/dexps [len(exps)]).  All four centres are differentiated explicitly."""
+    L = np.ascontiguousarray(shells["L"], dtype=np.int32)
+    K = np.ascontiguousarray(shells["K"], dtype=np.int32)
+    xyz = np.ascontiguousarray(shells["xyz"], dtype=np.float64).reshape(-1)
+    off = np.ascontiguousarray(shells["off"], dtype=np.int64)
+    exps = np.ascontiguousarray(shells["exps"], dtype=np.float64)
+    coefs = np.ascontiguousarray(shells["coefs"], dtype=np.float64)
+    q = np.ascontiguousarray(quartets, dtype=np.int32).reshape(-1, 4)
+    nq = q.shape[0]
+    w = np.ones(nq) if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    if (dl is None) == (density is None):
+        raise ValueError("give exactly one of dl and density")
+    keep = []
+    dl_off = None
+    nbf = 0
+    if dl is not None:
+        sizes = np.array([ncart(L[a]) * ncart(L[b]) * ncart(L[c]) * ncart(L[d]) for a, b, c, d in q],
+                         dtype=np.int64)
+        dl_off = np.zeros(max(nq, 1), dtype=np.int64)
+        if nq:
+            dl_off[1:nq] = np.cumsum(sizes)[:-1]
+        dl = np.ascontiguousarray(dl, dtype=np.float64)
+        keep += [dl, dl_off]
+        dl_p, off_p, d_p = dl.ctypes.data, dl_off.ctypes.data, None
+    else:
+        density = np.ascontiguousarray(density, dtype=np.float64)
+        nbf = density.shape[0]
+        keep.append(density)
+        dl_p, off_p, d_p = None, None, density.ctypes.data
+    gx = np.zeros(3 * len(L))
+    ge = np.zeros(max(len(exps), 1))
+    en = np.zeros(1)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = load().oracle_gradient(len(L), L, K, xyz, off, exps, coefs, nq,
+                                q.reshape(-1) if nq else np.zeros(4, np.int32), w if nq else np.zeros(1),
+                                dl_p, off_p, d_p, nbf, gx, ge, en, int(n_threads))
+    if rc != 0:
+        raise ValueError("oracle_gradient: bad arguments (rc=%d)" % rc)
+    return float(en[0]), gx.reshape(-1, 3), ge[:len(exps)]

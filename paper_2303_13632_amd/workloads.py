@@ -171,6 +171,19 @@ def gradient_basis(seed=SEED_BASE + 4):
                           heavy_sites=heavy)
 
 
+def random_shells(n, lmax=2, seed=SEED_BASE + 6, box=4.0, k_choices=(1, 2, 3), exp_range=(0.1, 100.0)):
+    """n shells with L uniform in 0..lmax, K uniform in k_choices, centres
+    uniform in [0, box)^3 Bohr, exponents log-uniform in exp_range,
+    coefficients uniform in [0.1, 1]."""
+    rng = np.random.default_rng(seed)
+    L = rng.integers(0, lmax + 1, size=n)
+    K = rng.choice(np.asarray(k_choices), size=n)
+    xyz = rng.uniform(0.0, box, size=(n, 3))
+    exps = [_log_uniform(rng, exp_range[0], exp_range[1], int(k)) for k in K]
+    coefs = [rng.uniform(0.1, 1.0, size=int(k)) for k in K]
+    return _pack(L, K, xyz, exps, coefs)
+
+
 def random_density(nbf, seed=SEED_BASE + 5, sigma=0.1):
     """Random symmetric matrix with entries N(0, sigma)."""
     rng = np.random.default_rng(seed)
