@@ -157,6 +157,34 @@ int eri_compress(int32_t bits, const double* eri, int64_t n_blocks, const int64_
 int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_t n_blocks,
                    const int64_t* block_off, double* out, void* stream);
 
+/* Adjoint (gradients of a scalar that is linear in the ERIs).  With Gbar
+ * either dL/d(ab|cd) (dl_deri: device FP64 in the plan layout of eri_compute's
+ * out_eri, one value per ERI) or D_mu,nu D_lam,sig from a symmetric density
+ * (density: device FP64, row-major nbf x nbf, basis functions numbered shell
+ * by shell in shell order with the component order above), the scalar is
+ *   L = sum over planned quartets of w_q sum_(abcd) Gbar (ab|cd),
+ * with w_q = 1 for explicit plans and, for ERI_PLAN_ALL_QUARTETS plans with a
+ * density, the degeneracy of the unique quartet (2 for a != b, 2 for c != d,
+ * 2 for (ab) != (cd)), so that L = sum_(mu nu lam sig) D D (mu nu|lam sig).
+ * Exactly one of dl_deri and density is given.  The call ADDS dL/dR to
+ * grad_centers (device, 3 per shell, the shell's centre xyz) and dL/dalpha to
+ * grad_exps (device, one per primitive, indexed like exps: prim_off[s] + k),
+ * and L itself to *energy (device, optional).  The coefficients are constants.
+ * Derivatives follow from the differentiated Gaussians (centre: 2 alpha
+ * g(a+1) - a g(a-1); exponent: N[(3/4 + L/2)/alpha g(a) - sum g(a+2)]) as
+ * contracted ERIs of derived shells computed by the FP64 class kernels,
+ * whatever the plan's precision; the fourth centre's derivative follows from
+ * translation invariance.  Accumulation uses FP64 atomics, so the summation
+ * order (and the last bits) may vary between calls.
+ * Returns ERI_EUNSUPPORTED when a shell of the plan has L > 2 (the exponent
+ * derivative of an L shell needs L+2 integrals, computed up to g),
+ * ERI_ESTATE for dl_deri with a plan whose output ring holds fewer quartets
+ * than it computes, ERI_EINVAL for a density whose nbf does not match.  The
+ * first call builds the derived pair tables (host and device memory held by
+ * the plan until eri_plan_destroy). */
+int eri_backward(eri_plan* plan, void* stream, const double* dl_deri, const double* density, int64_t nbf,
+                 double* grad_centers, double* grad_exps, double* energy);
+
 void eri_plan_destroy(eri_plan* plan);
 
 const char* eri_status_string(int status);

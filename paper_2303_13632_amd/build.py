@@ -54,7 +54,7 @@ def _compile(src, obj, deps):
     return obj, time.time() - t0, True
 
 
-def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=range(256)):
+def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=None):
     sys.path.insert(0, CSRC)
     import codegen  # noqa: E402
     import gen_boys_table  # noqa: E402
@@ -65,8 +65,9 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=range(2
     if not os.path.exists(bt):
         gen_boys_table.write(bt)
     files, _ = codegen.generate(GEN, precisions=precisions, classes=classes)
-    deps = [os.path.join(CSRC, f) for f in ("eri_device.h", "eri_plan_types.h", "eri_dispatch.h")] + [bt]
-    srcs = files + [os.path.join(CSRC, "eri_lib.hip")]
+    deps = [os.path.join(CSRC, f) for f in ("eri_device.h", "eri_plan_types.h", "eri_dispatch.h",
+                                            "eri_internal.h")] + [bt]
+    srcs = files + [os.path.join(CSRC, "eri_lib.hip"), os.path.join(CSRC, "eri_backward.hip")]
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     t0 = time.time()

@@ -79,6 +79,24 @@ def class_id(la, lb, lc, ld):
     return la * 64 + lb * 16 + lc * 4 + ld
 
 
+def class_id5(la, lb, lc, ld):
+    """Index of a class in the kernel table (angular momenta up to 4)."""
+    return la * 125 + lb * 25 + lc * 5 + ld
+
+
+def kernel_name(prec, user):
+    """eri_<prec>_cNNN for s-f classes (NNN = La*64+Lb*16+Lc*4+Ld), eri_<prec>_gNNN
+    (NNN = La*125+Lb*25+Lc*5+Ld) for classes with a g shell (derivative shells)."""
+    if max(user) <= 3:
+        return "eri_%s_c%03d" % (prec, class_id(*user))
+    return "eri_%s_g%03d" % (prec, class_id5(*user))
+
+
+# classes with one g shell and s, p, d on the others: the exponent derivatives
+# of d shells (L + 2) in the adjoint
+G_CLASSES = [c for c in itertools.product(range(5), repeat=4) if sorted(c)[-1] == 4 and sorted(c)[-2] <= 2]
+
+
 def class_of(cid):
     return (cid >> 6) & 3, (cid >> 4) & 3, (cid >> 2) & 3, cid & 3
 
@@ -324,7 +342,7 @@ def emit_mode_T(cp, prec):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
-    name = "eri_%s_c%03d" % (prec, cp.cid)
+    name = kernel_name(prec, cp.user)
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode T, %s" % (cp.user + (cp.perm, a, b, c, d, prec)))
     em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
@@ -488,7 +506,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
-    name = "eri_%s_c%03d" % (prec, cp.cid)
+    name = kernel_name(prec, cp.user)
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     subs, EP = wave_layout(cp)
     S = len(subs)
@@ -519,7 +537,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
             else:
                 row += [0, 0, 0, 0, -1, ls, ls, ls]
         rows.append(row)
-    tbl = "eri_tbl_%s_c%03d" % (prec, cp.cid)
+    tbl = "eri_tbl_" + kernel_name(prec, cp.user)[4:]
     em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode W: %d lanes/slot, %d slot(s), %d subslot(s), %s"
        % (cp.user + (cp.perm, a, b, c, d, EP, NSLOT, S, prec)))
     em("static __constant__ signed char %s[%d][%d] = {" % (tbl, EP, 8 * S))
@@ -724,41 +742,45 @@ def kernel_info_init(cp, name):
     return "{(const void*)%s, 1, 64, %d, %d, %d, %d, %d, 0}" % (name, 64 // EP, cp.n_eriq, per_pq, per_q, pk)
 
 
-def generate(outdir, precisions=("fp64",), classes=range(256), group=8, overrides=None):
+def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None, g_classes=True):
     """Write kernel sources (grouped `group` classes per file, each with a host
     registration function filling its entries of the kernel table) and the
-    table TU; returns (list of source files, dict of ClassPlan)."""
+    table TU; returns (list of source files, dict of ClassPlan).  `classes`
+    is a list of (La, Lb, Lc, Ld); by default the 256 s-f classes in every
+    precision plus, in FP64 only, the classes with one g shell."""
     os.makedirs(outdir, exist_ok=True)
     overrides = overrides or {}
+    if classes is None:
+        classes = [class_of(c) for c in range(256)]
+    jobs = [(c, prec) for prec in precisions for c in classes]
+    if g_classes:
+        jobs += [(c, "fp64") for c in G_CLASSES]
     plans = {}
     files = []
     regs = []
-    classes = list(classes)
-    for g in range(0, len(classes), group):
-        chunk = classes[g:g + group]
-        for prec in precisions:
-            parts = [HEADER, '#include "eri_dispatch.h"']
-            reg = []
-            for cid in chunk:
-                la, lb, lc, ld = class_of(cid)
-                cp = plans.get(cid)
-                if cp is None:
-                    kw = overrides.get(cid, {})
-                    cp = ClassPlan(la, lb, lc, ld, **kw)
-                    plans[cid] = cp
-                name, src = emit_class(cp, prec)
-                parts.append(src)
-                reg.append("    t[%d] = %s;" % (cid, kernel_info_init(cp, name)))
+    for g in range(0, len(jobs), group):
+        chunk = jobs[g:g + group]
+        parts = [HEADER, '#include "eri_dispatch.h"']
+        reg = {}
+        for user, prec in chunk:
+            cp = plans.get(user)
+            if cp is None:
+                cp = ClassPlan(*user, **overrides.get(user, {}))
+                plans[user] = cp
+            name, src = emit_class(cp, prec)
+            parts.append(src)
+            reg.setdefault(prec, []).append("    t[%d] = %s;" % (class_id5(*user), kernel_info_init(cp, name)))
+        for prec, lines_ in reg.items():
             fname = "eri_register_%s_g%03d" % (prec, g // group)
-            parts.append("void %s(eri_kernel_info* t)\n{\n%s\n}\n" % (fname, "\n".join(reg)))
+            parts.append("void %s(eri_kernel_info* t)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
             regs.append((prec, fname))
-            fn = os.path.join(outdir, "eri_%s_g%03d.hip" % (prec, g // group))
-            write_if_changed(fn, "\n".join(parts))
-            files.append(fn)
+        fn = os.path.join(outdir, "eri_k%03d.hip" % (g // group))
+        write_if_changed(fn, "\n".join(parts))
+        files.append(fn)
     lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
     for prec, fname in regs:
         lines.append("void %s(eri_kernel_info* t);" % fname)
-    lines.append("static eri_kernel_info g_fp64[256], g_mixed[256];")
+    lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5];")
     lines.append("static std::once_flag g_once;")
     lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
     lines.append("{")

@@ -1,0 +1,578 @@
+// Adjoint of the contracted ERIs: gradients of L = sum_q w_q sum Gbar (ab|cd)
+// with respect to every shell centre and every primitive exponent, where
+// Gbar is dL/d(ab|cd) (given per ERI in the plan layout) or D_ab D_cd from a
+// symmetric density.
+//
+// Derivatives of a Cartesian Gaussian x^a exp(-alpha r^2) about its centre A:
+//   d/dA_x g_a = 2 alpha g_(a+1_x) - a_x g_(a-1_x),
+// and of the normalised primitive N(alpha, L) g_a with respect to alpha:
+//   d/dalpha (N g_a) = N [ (3/4 + L/2) / alpha g_a - sum_x g_(a+2_x) ].
+// Both are contracted ERIs of derived shells at the same centre, so the
+// forward class kernels compute them unchanged:
+//   s+  : L+1, coefficients 2 alpha c N(alpha,L) / N(alpha,L+1)
+//   s-  : L-1, coefficients c N(alpha,L) / N(alpha,L-1)
+//   s0k : L,   primitive k alone, coefficient c_k (3/4 + L/2) / alpha_k
+//   s2k : L+2, primitive k alone, coefficient -c_k N(alpha_k,L) / N(alpha_k,L+2)
+// (each derived coefficient times the N the kernel applies gives the factor
+// above).  Centres A, B, C are differentiated this way; the derivative with
+// respect to D follows from translation invariance, dA + dB + dC + dD = 0.
+//
+// Pipeline per class and chunk of quartets: user items (P1, P2) -> for each
+// derivative kind a derived item list (derive kernel) -> the forward kernel of
+// the derived class writes FP64 blocks into scratch -> the contraction kernel
+// maps each derived block onto Gbar and adds the sums into the gradients with
+// FP64 atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "eri_internal.h"
+
+using namespace eri_detail;
+
+namespace {
+
+enum { DK_BASE = -1, DK_PLUS = 0, DK_MINUS = 1, DK_E0 = 2, DK_E2 = 3 };
+
+constexpr int BWD_MAXL = 2;                       // shells of the differentiated basis
+constexpr int64_t BWD_SCRATCH_MAX = (int64_t)1 << 28;   // doubles (2 GiB)
+constexpr int64_t BWD_CHUNK_MAX = (int64_t)1 << 22;     // quartets per pass
+
+__host__ __device__ inline int kind_shift(int kind) { return kind == DK_PLUS ? 1 : kind == DK_MINUS ? -1 : kind == DK_E2 ? 2 : 0; }
+
+}  // namespace
+
+struct eri_bwd_state {
+    int64_t n_base = 0;          // base records (first in the table)
+    int32_t null_rec = 0;        // record with no primitive pairs: its blocks are zero
+    eri_shell_pair* d_pairs = nullptr;
+    eri_prim_pair* d_prims = nullptr;
+    int32_t* d_dmap = nullptr;   // per base record: [side a | side b][kind], sign bit = stored reversed
+    eri_item* d_uall = nullptr;  // explicit plans: user items in plan order
+    eri_item* d_uitems = nullptr;
+    eri_item* d_ditems = nullptr;
+    double* d_scratch = nullptr;
+    int64_t* d_bf = nullptr;     // first basis function of each shell
+    int64_t* d_poff = nullptr;   // first primitive of each shell (the caller's layout)
+    int64_t nbf = 0;
+    int64_t chunk_cap = 0;
+    int64_t scratch_elems = 0;
+    int kmax[BWD_MAXL + 1] = {};  // largest K among shells of each L
+};
+
+void eri_bwd_free(eri_bwd_state* b)
+{
+    if (!b) return;
+    void* ptrs[] = {b->d_pairs, b->d_prims, b->d_dmap, b->d_uall, b->d_uitems, b->d_ditems, b->d_scratch, b->d_bf, b->d_poff};
+    for (void* x : ptrs)
+        if (x) (void)hipFree(x);
+    delete b;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Device kernels
+// ---------------------------------------------------------------------------
+// Components (lx, ly, lz) of L = 0..4 in shell order (x^L first).
+__constant__ signed char c_comp[5][15][3] = {
+    {{0, 0, 0}},
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}},
+    {{3, 0, 0}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 1, 1}, {1, 0, 2}, {0, 3, 0}, {0, 2, 1}, {0, 1, 2}, {0, 0, 3}},
+    {{4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0}, {1, 2, 1}, {1, 1, 2}, {1, 0, 3},
+     {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3}, {0, 0, 4}},
+};
+
+__device__ __forceinline__ int comp_index(int lx, int ly, int lz)
+{
+    const int m = ly + lz;   // L - lx
+    return m * (m + 1) / 2 + lz;
+}
+
+// Derived items of one kind: the user item (P1, P2) with the pair `pair`
+// replaced by its derived record for user position `pos` of that pair, put in
+// the orientation of the derived class kernel (kswap: its bra is pair 2;
+// eq1/eq2: derived pair 1/2 has equal angular momenta, so a reversed record
+// is flagged for the kernel).
+__global__ __launch_bounds__(256) void eri_bwd_derive_kernel(const eri_item* __restrict__ uitems, int64_t n,
+                                                             const eri_shell_pair* __restrict__ pairs,
+                                                             const int32_t* __restrict__ dmap, int pair, int pos,
+                                                             int kind, int k, int32_t null_rec, int kswap, int eq1,
+                                                             int eq2, eri_item* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const eri_item u = uitems[i];
+    int32_t rec[2] = {u.bra & 0x7fffffff, u.ket & 0x7fffffff};
+    int rev[2] = {u.bra < 0 ? 1 : 0, u.ket < 0 ? 1 : 0};
+    if (kind >= 0) {
+        const int32_t pm = rec[pair];
+        const int side = pos ^ rev[pair];   // record side of the user position
+        const int32_t e = dmap[8 * (int64_t)pm + 4 * side + kind];
+        int32_t r = e & 0x7fffffff;
+        const int f = e < 0 ? 1 : 0;
+        if (kind >= DK_E0) {
+            const eri_shell_pair P = pairs[pm];
+            const int K = side == 0 ? P.nprim / P.kb : P.kb;
+            r = k < K ? r + k : null_rec;
+        }
+        rec[pair] = r;
+        rev[pair] ^= f;
+    }
+    const int32_t b1 = rec[0] | ((rev[0] && eq1) ? (int32_t)0x80000000 : 0);
+    const int32_t b2 = rec[1] | ((rev[1] && eq2) ? (int32_t)0x80000000 : 0);
+    eri_item o;
+    o.bra = kswap ? b2 : b1;
+    o.ket = kswap ? b1 : b2;
+    out[i] = o;
+}
+
+struct bwd_contract_args {
+    const eri_item* uitems;
+    int64_t n;
+    const eri_shell_pair* pairs;
+    const double* blk;          // derived blocks, one per user item
+    const double* dl;           // dL/dERI in plan layout, or null
+    int64_t dl_base;            // index in dl of the first ERI of the pass's first quartet
+    const double* dens;         // density (nbf x nbf), or null
+    int64_t nbf;
+    const int64_t* bf;
+    const int64_t* poff;
+    double* grad_c;
+    double* grad_e;
+    double* energy;
+    int32_t L[4];               // user angular momenta of the class
+    int32_t pos;                // differentiated user position (kinds other than base)
+    int32_t kind;
+    int32_t k;                  // primitive of the differentiated shell (exponent kinds)
+    int32_t degen;              // weight quartets by their degeneracy in the full sum
+};
+
+// One wavefront per user quartet: sum over its ERIs of Gbar times the mapped
+// derived ERIs, then one atomic add per gradient entry.
+__global__ __launch_bounds__(64) void eri_bwd_contract_kernel(bwd_contract_args A)
+{
+    const int64_t i = blockIdx.x;
+    const int lane = threadIdx.x;
+    const eri_item u = A.uitems[i];
+    const int32_t p1 = u.bra & 0x7fffffff, p2 = u.ket & 0x7fffffff;
+    const eri_shell_pair P1 = A.pairs[p1], P2 = A.pairs[p2];
+    int32_t sh[4];
+    sh[0] = u.bra < 0 ? P1.sb : P1.sa;
+    sh[1] = u.bra < 0 ? P1.sa : P1.sb;
+    sh[2] = u.ket < 0 ? P2.sb : P2.sa;
+    sh[3] = u.ket < 0 ? P2.sa : P2.sb;
+    if (A.kind >= DK_E0) {
+        // primitive k of the differentiated shell: none when k >= K
+        const eri_shell_pair& P = A.pos < 2 ? P1 : P2;
+        const int side = (A.pos & 1) ^ ((A.pos < 2 ? u.bra : u.ket) < 0 ? 1 : 0);
+        const int K = side == 0 ? P.nprim / P.kb : P.kb;
+        if (A.k >= K) return;
+    }
+    int nc[4], nd[4];
+    for (int x = 0; x < 4; ++x) {
+        nc[x] = (A.L[x] + 1) * (A.L[x] + 2) / 2;
+        nd[x] = nc[x];
+    }
+    const int dpos = A.kind == DK_BASE ? 0 : A.pos;
+    const int Ld = A.L[dpos] + kind_shift(A.kind);
+    nd[dpos] = (Ld + 1) * (Ld + 2) / 2;
+    const int n_eriq = nc[0] * nc[1] * nc[2] * nc[3];
+    const int st[4] = {nd[1] * nd[2] * nd[3], nd[2] * nd[3], nd[3], 1};
+    const int64_t nblk = (int64_t)nd[0] * st[0];
+    const double* b = A.blk + i * nblk;
+    double w = 1.0;
+    if (A.degen) {
+        if (sh[0] != sh[1]) w *= 2.0;
+        if (sh[2] != sh[3]) w *= 2.0;
+        if (p1 != p2) w *= 2.0;
+    }
+    int64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+    if (!A.dl) {
+        f0 = A.bf[sh[0]]; f1 = A.bf[sh[1]]; f2 = A.bf[sh[2]]; f3 = A.bf[sh[3]];
+    }
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    for (int o = lane; o < n_eriq; o += 64) {
+        int ci[4];
+        int rem = o;
+        ci[3] = rem % nc[3]; rem /= nc[3];
+        ci[2] = rem % nc[2]; rem /= nc[2];
+        ci[1] = rem % nc[1]; rem /= nc[1];
+        ci[0] = rem;
+        double g;
+        if (A.dl) {
+            g = A.dl[A.dl_base + i * n_eriq + o];
+        } else {
+            g = A.dens[(f0 + ci[0]) * A.nbf + f1 + ci[1]] * A.dens[(f2 + ci[2]) * A.nbf + f3 + ci[3]];
+        }
+        if (g == 0.0) continue;
+        if (A.kind == DK_BASE || A.kind == DK_E0) {
+            acc0 += g * b[o];
+            continue;
+        }
+        int base = 0;
+        for (int x = 0; x < 4; ++x)
+            if (x != dpos) base += ci[x] * st[x];
+        const int sd = st[dpos];
+        const int La = A.L[dpos];
+        const int lx = c_comp[La][ci[dpos]][0], ly = c_comp[La][ci[dpos]][1], lz = c_comp[La][ci[dpos]][2];
+        if (A.kind == DK_PLUS) {
+            acc0 += g * b[base + comp_index(lx + 1, ly, lz) * sd];
+            acc1 += g * b[base + comp_index(lx, ly + 1, lz) * sd];
+            acc2 += g * b[base + comp_index(lx, ly, lz + 1) * sd];
+        } else if (A.kind == DK_MINUS) {
+            if (lx) acc0 -= g * lx * b[base + comp_index(lx - 1, ly, lz) * sd];
+            if (ly) acc1 -= g * ly * b[base + comp_index(lx, ly - 1, lz) * sd];
+            if (lz) acc2 -= g * lz * b[base + comp_index(lx, ly, lz - 1) * sd];
+        } else {
+            acc0 += g * (b[base + comp_index(lx + 2, ly, lz) * sd] + b[base + comp_index(lx, ly + 2, lz) * sd] +
+                         b[base + comp_index(lx, ly, lz + 2) * sd]);
+        }
+    }
+    for (int s = 32; s > 0; s >>= 1) {
+        acc0 += __shfl_xor(acc0, s);
+        acc1 += __shfl_xor(acc1, s);
+        acc2 += __shfl_xor(acc2, s);
+    }
+    if (lane != 0) return;
+    acc0 *= w; acc1 *= w; acc2 *= w;
+    if (A.kind == DK_BASE) {
+        atomicAdd(A.energy, acc0);
+    } else if (A.kind == DK_PLUS || A.kind == DK_MINUS) {
+        const double v[3] = {acc0, acc1, acc2};
+        for (int x = 0; x < 3; ++x) {
+            atomicAdd(A.grad_c + 3 * (int64_t)sh[dpos] + x, v[x]);
+            atomicAdd(A.grad_c + 3 * (int64_t)sh[3] + x, -v[x]);
+        }
+    } else {
+        atomicAdd(A.grad_e + A.poff[sh[dpos]] + A.k, acc0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host: derived shells, derived pair records and the per-record map
+// ---------------------------------------------------------------------------
+struct ext_shells {
+    std::vector<int32_t> L, K;
+    std::vector<double> xyz, exps, coefs;
+    std::vector<int64_t> off;
+    shell_set view() const
+    {
+        return shell_set{(int64_t)L.size(), L.data(), K.data(), xyz.data(), off.data(), exps.data(), coefs.data()};
+    }
+    int32_t add(int l, const double* c3, int k, const double* ex, const double* cf)
+    {
+        const int32_t id = (int32_t)L.size();
+        L.push_back(l);
+        K.push_back(k);
+        xyz.insert(xyz.end(), c3, c3 + 3);
+        off.push_back((int64_t)exps.size());
+        exps.insert(exps.end(), ex, ex + k);
+        coefs.insert(coefs.end(), cf, cf + k);
+        return id;
+    }
+};
+
+// Stored orientation of the derived pair (x, y) given in base-record order:
+// larger angular momentum first; equal ones by the VRR score.  Returns true
+// when the record is stored as (y, x).
+bool stored_reversed(const shell_set& s, int32_t x, int32_t y, bool by_score)
+{
+    if (s.L[x] != s.L[y]) return s.L[x] < s.L[y];
+    return by_score && x != y && vrr_score(s, y, x) < vrr_score(s, x, y);
+}
+
+int build_state(eri_plan* p, eri_bwd_state*& out)
+{
+    eri_bwd_state* st = new (std::nothrow) eri_bwd_state();
+    if (!st) return ERI_ENOMEM;
+    const int64_t ns = (int64_t)p->sh_L.size();
+    const shell_set orig{ns, p->sh_L.data(), p->sh_K.data(), p->sh_xyz.data(), p->sh_off.data(), p->sh_exps.data(),
+                         p->sh_coefs.data()};
+    // ---- base records (canonical orientation) and user items --------------
+    std::vector<uint64_t> base_keys;
+    std::vector<eri_item> uall;
+    if (p->batched) {
+        base_keys.resize(p->h_pairs.size());
+        for (size_t i = 0; i < p->h_pairs.size(); ++i)
+            base_keys[i] = ((uint64_t)(uint32_t)p->h_pairs[i].sa << 32) | (uint32_t)p->h_pairs[i].sb;
+    } else {
+        const int64_t nq = p->n_quartets;
+        std::vector<uint64_t> keys(2 * nq);
+        std::vector<uint8_t> rv(2 * nq);
+        for (int64_t j = 0; j < nq; ++j)
+            for (int h = 0; h < 2; ++h) {
+                int32_t x = p->quartets[4 * j + 2 * h], y = p->quartets[4 * j + 2 * h + 1];
+                const bool r = stored_reversed(orig, x, y, true);
+                if (r) std::swap(x, y);
+                keys[2 * j + h] = ((uint64_t)(uint32_t)x << 32) | (uint32_t)y;
+                rv[2 * j + h] = r ? 1 : 0;
+            }
+        base_keys = keys;
+        std::sort(base_keys.begin(), base_keys.end());
+        base_keys.erase(std::unique(base_keys.begin(), base_keys.end()), base_keys.end());
+        uall.resize(nq);
+        for (int64_t j = 0; j < nq; ++j) {
+            int32_t r[2];
+            for (int h = 0; h < 2; ++h) {
+                const int64_t idx = std::lower_bound(base_keys.begin(), base_keys.end(), keys[2 * j + h]) - base_keys.begin();
+                r[h] = (int32_t)idx | (rv[2 * j + h] ? (int32_t)0x80000000 : 0);
+            }
+            uall[j].bra = r[0];
+            uall[j].ket = r[1];
+        }
+    }
+    const int64_t nb = (int64_t)base_keys.size();
+    // ---- derived shells ------------------------------------------------------
+    ext_shells ex;
+    ex.L.assign(orig.L, orig.L + ns);
+    ex.K.assign(orig.K, orig.K + ns);
+    ex.xyz.assign(orig.xyz, orig.xyz + 3 * ns);
+    ex.off.assign(orig.off, orig.off + ns);
+    ex.exps = p->sh_exps;
+    ex.coefs = p->sh_coefs;
+    std::vector<int32_t> plus(ns), minus(ns, -1), e0(ns), e2(ns);
+    for (int64_t s = 0; s < ns; ++s) {
+        const int L = orig.L[s], K = orig.K[s];
+        const double* c3 = orig.xyz + 3 * s;
+        const double* al = orig.exps + orig.off[s];
+        const double* cf = orig.coefs + orig.off[s];
+        std::vector<double> c(K);
+        for (int k = 0; k < K; ++k) c[k] = 2.0 * al[k] * cf[k] * norm_axis(al[k], L) / norm_axis(al[k], L + 1);
+        plus[s] = ex.add(L + 1, c3, K, al, c.data());
+        if (L >= 1) {
+            for (int k = 0; k < K; ++k) c[k] = cf[k] * norm_axis(al[k], L) / norm_axis(al[k], L - 1);
+            minus[s] = ex.add(L - 1, c3, K, al, c.data());
+        }
+        for (int k = 0; k < K; ++k) {
+            const double v = cf[k] * (0.75 + 0.5 * L) / al[k];
+            const int32_t id = ex.add(L, c3, 1, al + k, &v);
+            if (k == 0) e0[s] = id;
+        }
+        for (int k = 0; k < K; ++k) {
+            const double v = -cf[k] * norm_axis(al[k], L) / norm_axis(al[k], L + 2);
+            const int32_t id = ex.add(L + 2, c3, 1, al + k, &v);
+            if (k == 0) e2[s] = id;
+        }
+        if (L <= BWD_MAXL) st->kmax[L] = std::max(st->kmax[L], K);
+    }
+    const shell_set es = ex.view();
+    // ---- derived pair keys and the map --------------------------------------
+    std::vector<uint64_t> keys(base_keys);
+    std::vector<int32_t> dmap(8 * nb, 0);
+    std::vector<int32_t> null_slots;   // dmap entries to point at the null record
+    auto key = [](int32_t x, int32_t y) { return ((uint64_t)(uint32_t)x << 32) | (uint32_t)y; };
+    for (int64_t i = 0; i < nb; ++i) {
+        const int32_t sa = (int32_t)(base_keys[i] >> 32), sb = (int32_t)(base_keys[i] & 0xffffffffu);
+        for (int side = 0; side < 2; ++side) {
+            const int32_t s = side ? sb : sa, o = side ? sa : sb;
+            // a derived pair in base-record order (x, y) = side a: (d, o); side b: (o, d)
+            auto put = [&](int kind, int32_t d, int count, bool by_score) {
+                const int32_t x = side ? o : d, y = side ? d : o;
+                const bool r = stored_reversed(es, x, y, by_score);
+                dmap[8 * i + 4 * side + kind] = (int32_t)keys.size() | (r ? (int32_t)0x80000000 : 0);
+                for (int k = 0; k < count; ++k) {
+                    const int32_t dk = d + k;
+                    const int32_t xx = side ? o : dk, yy = side ? dk : o;
+                    keys.push_back(r ? key(yy, xx) : key(xx, yy));
+                }
+            };
+            put(DK_PLUS, plus[s], 1, true);
+            if (minus[s] >= 0) put(DK_MINUS, minus[s], 1, true);
+            else null_slots.push_back((int32_t)(8 * i + 4 * side + DK_MINUS));
+            put(DK_E0, e0[s], orig.K[s], false);
+            put(DK_E2, e2[s], orig.K[s], false);
+        }
+    }
+    if ((int64_t)keys.size() + 1 > INT32_MAX) {
+        delete st;
+        return ERI_EUNSUPPORTED;
+    }
+    std::vector<eri_shell_pair> pairs;
+    std::vector<eri_prim_pair> prims;
+    build_pair_tables(es, keys, pairs, prims);
+    // the null record: no primitive pairs
+    eri_shell_pair nr;
+    std::memset(&nr, 0, sizeof(nr));
+    nr.kb = 1;
+    st->null_rec = (int32_t)pairs.size();
+    pairs.push_back(nr);
+    for (int32_t slot : null_slots) dmap[slot] = st->null_rec;
+    st->n_base = nb;
+    // ---- basis-function offsets ----------------------------------------------
+    std::vector<int64_t> bf(ns + 1, 0);
+    for (int64_t s = 0; s < ns; ++s) bf[s + 1] = bf[s] + ncart(orig.L[s]);
+    st->nbf = bf[ns];
+    // ---- pass sizes ------------------------------------------------------------
+    int64_t maxcount = 0, maxnd = 1;
+    for (int c = 0; c < 256; ++c) {
+        if (!p->class_count[c]) continue;
+        const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
+        int64_t base = 1;
+        for (int x = 0; x < 4; ++x) base *= ncart(L[x]);
+        int64_t nd = base;
+        for (int x = 0; x < 4; ++x) nd = std::max<int64_t>(nd, base / ncart(L[x]) * ncart(L[x] + 2));
+        maxcount = std::max(maxcount, p->class_count[c]);
+        maxnd = std::max(maxnd, nd);
+    }
+    st->chunk_cap = std::max<int64_t>(1, std::min({maxcount, BWD_CHUNK_MAX, BWD_SCRATCH_MAX / maxnd}));
+    st->scratch_elems = st->chunk_cap * maxnd;
+    int rc = ERI_OK;
+    auto up = [&](void** dst, const void* src, size_t bytes) {
+        if (rc == ERI_OK) rc = upload(p, dst, src, bytes);
+    };
+    up((void**)&st->d_pairs, pairs.data(), pairs.size() * sizeof(eri_shell_pair));
+    up((void**)&st->d_prims, prims.empty() ? nullptr : prims.data(), prims.size() * sizeof(eri_prim_pair));
+    up((void**)&st->d_dmap, dmap.empty() ? nullptr : dmap.data(), dmap.size() * sizeof(int32_t));
+    if (!p->batched) up((void**)&st->d_uall, uall.empty() ? nullptr : uall.data(), uall.size() * sizeof(eri_item));
+    else up((void**)&st->d_uitems, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
+    up((void**)&st->d_ditems, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
+    up((void**)&st->d_scratch, nullptr, (size_t)st->scratch_elems * sizeof(double));
+    up((void**)&st->d_bf, bf.data(), bf.size() * sizeof(int64_t));
+    up((void**)&st->d_poff, p->sh_off.empty() ? nullptr : p->sh_off.data(), p->sh_off.size() * sizeof(int64_t));
+    if (rc != ERI_OK) {
+        eri_bwd_free(st);
+        return rc;
+    }
+    out = st;
+    return ERI_OK;
+}
+
+struct bwd_kind {
+    int pos;    // user position 0..3 (0 for the base kind)
+    int kind;
+    int k;
+};
+
+int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const double* dl, const double* dens,
+              double* grad_c, double* grad_e, double* energy)
+{
+    const int64_t n = p->class_count[c];
+    const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
+    const eri_kernel_info* tab = kernel_table(ERI_FP64);
+    std::vector<bwd_kind> kinds;
+    if (energy) kinds.push_back({0, DK_BASE, 0});
+    for (int x = 0; x < 3; ++x) {
+        kinds.push_back({x, DK_PLUS, 0});
+        if (L[x] >= 1) kinds.push_back({x, DK_MINUS, 0});
+    }
+    for (int x = 0; x < 4; ++x)
+        for (int k = 0; k < st->kmax[L[x]]; ++k) {
+            kinds.push_back({x, DK_E0, k});
+            kinds.push_back({x, DK_E2, k});
+        }
+    int64_t maxnd = 1;
+    for (const auto& kd : kinds) {
+        int64_t nd = 1;
+        for (int x = 0; x < 4; ++x) nd *= ncart(L[x] + (kd.kind != DK_BASE && x == kd.pos ? kind_shift(kd.kind) : 0));
+        maxnd = std::max(maxnd, nd);
+    }
+    const int64_t chunk = std::max<int64_t>(1, std::min(st->chunk_cap, st->scratch_elems / maxnd));
+    const eri_batch_class* bc = nullptr;
+    if (p->batched) {
+        for (auto& b : p->bclass)
+            if (b.cid == c) bc = &b;
+        if (!bc) return ERI_OK;
+    }
+    const int n_eriq = ncart(L[0]) * ncart(L[1]) * ncart(L[2]) * ncart(L[3]);
+    for (int64_t q0 = 0; q0 < n; q0 += chunk) {
+        const int64_t q1 = std::min(n, q0 + chunk), m = q1 - q0;
+        const eri_item* uitems;
+        if (p->batched) {
+            const auto sbeg = p->h_seg_off.begin();
+            const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q0) - sbeg) - 1;
+            const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q1) - sbeg);
+            if (s1 - s0 > INT32_MAX) return ERI_EUNSUPPORTED;
+            hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, strm, p->d_seg_off,
+                               p->d_seg_p1, s0, bc->ket_lo, q0, q1, 0, st->d_uitems);
+            ERI_HIP_TRY(hipGetLastError());
+            uitems = st->d_uitems;
+        } else {
+            uitems = st->d_uall + p->class_qoff[c] + q0;
+        }
+        for (const auto& kd : kinds) {
+            int Lp[4] = {L[0], L[1], L[2], L[3]};
+            if (kd.kind != DK_BASE) Lp[kd.pos] += kind_shift(kd.kind);
+            const eri_kernel_info& ki = tab[class_id5(Lp[0], Lp[1], Lp[2], Lp[3])];
+            if (!ki.fn) return ERI_EUNSUPPORTED;
+            const int kswap = (ki.perm & 3) >= 2 ? 1 : 0;
+            const unsigned g256 = (unsigned)((m + 255) / 256);
+            hipLaunchKernelGGL(eri_bwd_derive_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, st->d_pairs, st->d_dmap,
+                               kd.pos / 2, kd.pos % 2, kd.kind, kd.k, st->null_rec, kswap, Lp[0] == Lp[1] ? 1 : 0,
+                               Lp[2] == Lp[3] ? 1 : 0, st->d_ditems);
+            ERI_HIP_TRY(hipGetLastError());
+            eri_class_args a;
+            std::memset(&a, 0, sizeof(a));
+            a.items = st->d_ditems;
+            a.n_items = m;
+            a.pairs = st->d_pairs;
+            a.prims = st->d_prims;
+            a.out_eri = st->d_scratch;
+            a.ring = m;
+            a.qbase = 0;
+            const int64_t grid = (m + ki.per_block - 1) / ki.per_block;
+            if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
+            void* args[] = {&a};
+            ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, strm));
+            bwd_contract_args ca;
+            std::memset(&ca, 0, sizeof(ca));
+            ca.uitems = uitems;
+            ca.n = m;
+            ca.pairs = st->d_pairs;
+            ca.blk = st->d_scratch;
+            ca.dl = dl;
+            ca.dl_base = p->class_eoff[c] + q0 * (int64_t)n_eriq;
+            ca.dens = dens;
+            ca.nbf = st->nbf;
+            ca.bf = st->d_bf;
+            ca.poff = st->d_poff;
+            ca.grad_c = grad_c;
+            ca.grad_e = grad_e;
+            ca.energy = energy;
+            for (int x = 0; x < 4; ++x) ca.L[x] = L[x];
+            ca.pos = kd.pos;
+            ca.kind = kd.kind;
+            ca.k = kd.k;
+            ca.degen = p->batched ? 1 : 0;
+            hipLaunchKernelGGL(eri_bwd_contract_kernel, dim3((unsigned)m), dim3(64), 0, strm, ca);
+            ERI_HIP_TRY(hipGetLastError());
+        }
+    }
+    return ERI_OK;
+}
+
+}  // namespace
+
+extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, const double* density, int64_t nbf,
+                            double* grad_centers, double* grad_exps, double* energy)
+{
+    if (!p || !grad_centers || !grad_exps) return ERI_EINVAL;
+    if ((dl_deri == nullptr) == (density == nullptr)) return ERI_EINVAL;
+    for (int32_t l : p->sh_L)
+        if (l > BWD_MAXL) return ERI_EUNSUPPORTED;
+    if (dl_deri && p->batched)
+        for (int c = 0; c < 256; ++c)
+            if (p->class_ring[c] != p->class_count[c]) return ERI_ESTATE;
+    int cur = 0;
+    ERI_HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
+    int rc = ERI_OK;
+    if (!p->bwd) {
+        try {
+            rc = build_state(p, p->bwd);
+        } catch (const std::bad_alloc&) {
+            rc = ERI_ENOMEM;
+        }
+    }
+    if (rc == ERI_OK && density && nbf != p->bwd->nbf) rc = ERI_EINVAL;
+    for (int c = 0; c < 256 && rc == ERI_OK; ++c)
+        if (p->class_count[c])
+            rc = run_class(p, p->bwd, c, (hipStream_t)stream, dl_deri, density, grad_centers, grad_exps, energy);
+    if (cur != p->device) (void)hipSetDevice(cur);
+    return rc;
+}

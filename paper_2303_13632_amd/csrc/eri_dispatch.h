@@ -14,6 +14,8 @@ struct eri_kernel_info {
     int32_t pad;
 };
 
-// Kernel table of a precision (0: FP64, 1: FP32-mixed); entries of classes
+// Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by
+// La*125 + Lb*25 + Lc*5 + Ld (angular momenta up to 4); entries of classes
 // without a kernel have fn == nullptr.
+#define ERI_NCLASS5 625
 const eri_kernel_info* eri_kernel_table(int precision);

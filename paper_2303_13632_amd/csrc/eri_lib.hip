@@ -14,31 +14,12 @@
 #include <thread>
 #include <vector>
 
-#include "eri.h"
 #include "eri_device.h"
-#include "eri_dispatch.h"
-#include "eri_plan_types.h"
+#include "eri_internal.h"
 
-namespace {
+namespace eri_detail {
 
 thread_local int g_last_hip = 0;
-
-#define ERI_HIP_TRY(expr)                                                  \
-    do {                                                                   \
-        hipError_t _e = (expr);                                            \
-        if (_e != hipSuccess) {                                            \
-            g_last_hip = (int)_e;                                          \
-            return _e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP;      \
-        }                                                                  \
-    } while (0)
-
-#define ERI_TRY(expr)                  \
-    do {                               \
-        int _rc = (expr);              \
-        if (_rc != ERI_OK) return _rc; \
-    } while (0)
-
-inline int ncart(int L) { return (L + 1) * (L + 2) / 2; }
 
 // N(alpha, L) of eq. 1: (2 alpha/pi)^(3/4) (4 alpha)^(L/2) / sqrt((2L-1)!!)
 double norm_axis(double alpha, int L)
@@ -47,37 +28,6 @@ double norm_axis(double alpha, int L)
     for (int k = 2 * L - 1; k > 1; k -= 2) df *= k;
     return std::pow(2.0 * alpha / M_PI, 0.75) * std::pow(4.0 * alpha, 0.5 * L) / std::sqrt(df);
 }
-
-// Run f(lo, hi) over [0, n) split across host threads.
-template <typename F>
-void parallel_for(int64_t n, F f)
-{
-    unsigned nt = std::thread::hardware_concurrency();
-    nt = nt == 0 ? 1 : (nt > 32 ? 32 : nt);
-    if (n < 65536 || nt == 1) {
-        f((int64_t)0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    const int64_t chunk = (n + nt - 1) / nt;
-    for (unsigned t = 0; t < nt; ++t) {
-        const int64_t lo = t * chunk, hi = std::min<int64_t>(n, lo + chunk);
-        if (lo >= hi) break;
-        th.emplace_back([=] { f(lo, hi); });
-    }
-    for (auto& x : th) x.join();
-}
-
-// Host view of the caller's shell set.
-struct shell_set {
-    int64_t n;
-    const int32_t* L;
-    const int32_t* K;
-    const double* xyz;
-    const int64_t* off;
-    const double* exps;
-    const double* coefs;
-};
 
 // A pair of equal angular momenta may go either way round; the VRR is put on
 // the centre that keeps max_ij K_ij (1 + |P_ij - A|)^(2L) small, i.e. where
@@ -155,78 +105,13 @@ void build_pair_tables(const shell_set& s, const std::vector<uint64_t>& keys, st
     });
 }
 
-}  // namespace
 
-// One batched class: the quartets (P1 | P2) of a bra pair class and a ket
-// pair class, enumerated as segments: for each bra pair P1 a prefix of the
-// Q-sorted ket pair list.
-struct eri_batch_class {
-    int cid = -1;
-    bool swap = false;              // kernel's computed bra is P2
-    int64_t n_quartets = 0;
-    int64_t seg_lo = 0, seg_hi = 0; // range in the plan's segment arrays
-    int64_t ket_lo = 0;             // first ket pair (global index) of the ket class
-    int64_t ring = 0;               // output slots
-    int64_t chunk = 0;              // quartets per launch (<= ring: no two quartets of
-                                    // one launch share a ring slot)
-};
-
-struct eri_plan {
-    int device = 0;
-    int precision = ERI_FP64;
-    int bits = 0;
-    int code_bytes = 0;
-    double cn = 0.0, qmax = 0.0;
-    bool batched = false;
-    int64_t n_quartets = 0, n_eri = 0, n_prim_quartets = 0;
-    std::vector<int64_t> pos;       // explicit plans: user quartet -> plan position
-    std::vector<int64_t> eri_off;   // explicit plans: user quartet -> first ERI
-    std::vector<int32_t> quartets;  // explicit plans: user quartets in plan order
-    int64_t class_count[256] = {};
-    int64_t class_ring[256] = {};
-    int64_t class_qoff[257] = {};
-    int64_t class_eoff[257] = {};
-    double class_flops[256] = {};
-    int64_t n_pairs = 0, n_prims = 0;
-    std::vector<eri_shell_pair> h_pairs;   // batched plans keep the pair table on the host
-    eri_shell_pair* d_pairs = nullptr;
-    eri_prim_pair* d_prims = nullptr;
-    eri_item* d_items = nullptr;
-    int64_t device_bytes = 0;
-    // batched plans
-    std::vector<eri_batch_class> bclass;
-    std::vector<int64_t> h_seg_off;     // quartet offset of each segment within its class
-    std::vector<int32_t> h_seg_p1;
-    int64_t* d_seg_off = nullptr;
-    int32_t* d_seg_p1 = nullptr;
-    int64_t chunk_cap = 0;
-    double schwarz = 0.0;
-    std::vector<double> pair_q;
-    hipGraphExec_t graph = nullptr;
-    const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
-};
-
-static const eri_kernel_info* kernel_table(int precision)
+const eri_kernel_info* kernel_table(int precision)
 {
     return eri_kernel_table(precision == ERI_FP32_MIXED ? 1 : 0);
 }
 
-static void plan_free(eri_plan* p)
-{
-    if (!p) return;
-    int cur = 0;
-    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
-    if (p->graph) (void)hipGraphExecDestroy(p->graph);
-    if (p->d_pairs) (void)hipFree(p->d_pairs);
-    if (p->d_prims) (void)hipFree(p->d_prims);
-    if (p->d_items) (void)hipFree(p->d_items);
-    if (p->d_seg_off) (void)hipFree(p->d_seg_off);
-    if (p->d_seg_p1) (void)hipFree(p->d_seg_p1);
-    if (cur != p->device) (void)hipSetDevice(cur);
-    delete p;
-}
-
-static int upload(eri_plan* p, void** dst, const void* src, size_t bytes)
+int upload(eri_plan* p, void** dst, const void* src, size_t bytes)
 {
     if (bytes == 0) bytes = 64;
     hipError_t e = hipMalloc(dst, bytes);
@@ -244,6 +129,26 @@ static int upload(eri_plan* p, void** dst, const void* src, size_t bytes)
         }
     }
     return ERI_OK;
+}
+
+}  // namespace eri_detail
+
+using namespace eri_detail;
+
+static void plan_free(eri_plan* p)
+{
+    if (!p) return;
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess && cur != p->device) (void)hipSetDevice(p->device);
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    if (p->d_pairs) (void)hipFree(p->d_pairs);
+    if (p->d_prims) (void)hipFree(p->d_prims);
+    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_seg_off) (void)hipFree(p->d_seg_off);
+    if (p->d_seg_p1) (void)hipFree(p->d_seg_p1);
+    if (p->bwd) eri_bwd_free(p->bwd);
+    if (cur != p->device) (void)hipSetDevice(cur);
+    delete p;
 }
 
 static int check_shells(const shell_set& s)
@@ -271,14 +176,14 @@ static int create_explicit(eri_plan* p, const shell_set& s, const int32_t* quart
     for (int64_t t = 0; t < n_quartets; ++t) {
         const int32_t* q = quartets + 4 * t;
         const int c = s.L[q[0]] * 64 + s.L[q[1]] * 16 + s.L[q[2]] * 4 + s.L[q[3]];
-        if (!tab[c].fn) return ERI_EUNSUPPORTED;
+        if (!tab[class_id5_of(c)].fn) return ERI_EUNSUPPORTED;
         cls[t] = c;
     }
     std::vector<uint8_t> swp(n_quartets, 0);
     parallel_for(n_quartets, [&](int64_t lo, int64_t hi) {
         for (int64_t t = lo; t < hi; ++t) {
             const int32_t* q = quartets + 4 * t;
-            const int pm = tab[cls[t]].perm;
+            const int pm = tab[class_id5_of(cls[t])].perm;
             int32_t ba = q[pm & 3], bb = q[(pm >> 2) & 3];
             int32_t ka = q[(pm >> 4) & 3], kb = q[(pm >> 6) & 3];
             uint8_t f = 0;
@@ -330,19 +235,19 @@ static int create_explicit(eri_plan* p, const shell_set& s, const int32_t* quart
         p->class_count[cls[t]] += 1;
         const int64_t npq = (int64_t)pairs[bra[t]].nprim * pairs[ket[t]].nprim;
         p->n_prim_quartets += npq;
-        p->class_flops[cls[t]] += (double)npq * tab[cls[t]].flops_pq + (double)tab[cls[t]].flops_q;
+        p->class_flops[cls[t]] += (double)npq * tab[class_id5_of(cls[t])].flops_pq + (double)tab[class_id5_of(cls[t])].flops_q;
     }
     p->class_qoff[0] = 0;
     p->class_eoff[0] = 0;
     for (int c = 0; c < 256; ++c) {
         p->class_ring[c] = p->class_count[c];
         p->class_qoff[c + 1] = p->class_qoff[c] + p->class_count[c];
-        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_count[c] * (int64_t)tab[c].n_eriq;
+        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_count[c] * (int64_t)tab[class_id5_of(c)].n_eriq;
     }
     p->n_eri = p->class_eoff[256];
     for (int64_t t = 0; t < n_quartets; ++t) {
         const int c = cls[t];
-        p->eri_off[t] = p->class_eoff[c] + (p->pos[t] - p->class_qoff[c]) * (int64_t)tab[c].n_eriq;
+        p->eri_off[t] = p->class_eoff[c] + (p->pos[t] - p->class_qoff[c]) * (int64_t)tab[class_id5_of(c)].n_eriq;
     }
     p->n_pairs = (int64_t)pairs.size();
     p->n_prims = (int64_t)prims.size();
@@ -478,10 +383,10 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
             const int64_t b0 = cls_lo[cb], b1 = cls_lo[cb + 1], k0 = cls_lo[ck], k1 = cls_lo[ck + 1];
             if (b0 == b1 || k0 == k1) continue;
             const int cid = (cb / 4) * 64 + (cb % 4) * 16 + (ck / 4) * 4 + (ck % 4);
-            if (!tab[cid].fn) return ERI_EUNSUPPORTED;
+            if (!tab[class_id5_of(cid)].fn) return ERI_EUNSUPPORTED;
             eri_batch_class bc;
             bc.cid = cid;
-            bc.swap = (tab[cid].perm & 3) >= 2;
+            bc.swap = (tab[class_id5_of(cid)].perm & 3) >= 2;
             bc.ket_lo = k0;
             bc.seg_lo = (int64_t)p->h_seg_p1.size();
             int64_t q = 0;
@@ -504,7 +409,7 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
                 q += n;
                 const int64_t npq = (int64_t)p->h_pairs[b].nprim * kprim[n];
                 p->n_prim_quartets += npq;
-                flops += (double)npq * tab[cid].flops_pq + (double)n * tab[cid].flops_q;
+                flops += (double)npq * tab[class_id5_of(cid)].flops_pq + (double)n * tab[class_id5_of(cid)].flops_q;
             }
             bc.seg_hi = (int64_t)p->h_seg_p1.size();
             if (bc.seg_hi == bc.seg_lo) continue;
@@ -519,7 +424,7 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
     }
     // ---- output ring: every quartet is written; the ring keeps the last ------
     int64_t total_eri = 0;
-    for (auto& bc : p->bclass) total_eri += bc.n_quartets * (int64_t)tab[bc.cid].n_eriq;
+    for (auto& bc : p->bclass) total_eri += bc.n_quartets * (int64_t)tab[class_id5_of(bc.cid)].n_eriq;
     const int64_t per_eri = p->code_bytes > 0 ? p->code_bytes : 8;
     const double frac = (o->ring_bytes > 0 && total_eri * per_eri > o->ring_bytes)
                             ? (double)o->ring_bytes / (double)(total_eri * per_eri) : 1.0;
@@ -535,9 +440,9 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
     p->class_eoff[0] = 0;
     for (int c = 0; c < 256; ++c) {
         p->class_qoff[c + 1] = p->class_qoff[c] + p->class_ring[c];
-        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_ring[c] * (int64_t)tab[c].n_eriq;
+        p->class_eoff[c + 1] = p->class_eoff[c] + p->class_ring[c] * (int64_t)tab[class_id5_of(c)].n_eriq;
         p->n_quartets += p->class_count[c];
-        p->n_eri += p->class_count[c] * (int64_t)tab[c].n_eriq;
+        p->n_eri += p->class_count[c] * (int64_t)tab[class_id5_of(c)].n_eriq;
     }
     ERI_TRY(upload(p, (void**)&p->d_pairs, p->h_pairs.empty() ? nullptr : p->h_pairs.data(),
                    p->h_pairs.size() * sizeof(eri_shell_pair)));
@@ -590,6 +495,14 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
         return ERI_EHIP;
     }
     try {
+        int64_t nprim_all = 0;
+        for (int64_t i = 0; i < n_shells; ++i) nprim_all = std::max<int64_t>(nprim_all, prim_off[i] + K[i]);
+        p->sh_L.assign(L, L + n_shells);
+        p->sh_K.assign(K, K + n_shells);
+        p->sh_xyz.assign(xyz, xyz + 3 * n_shells);
+        p->sh_off.assign(prim_off, prim_off + n_shells);
+        p->sh_exps.assign(exps, exps + nprim_all);
+        p->sh_coefs.assign(coefs, coefs + nprim_all);
         rc = batched ? create_batched(p, s, opts) : create_explicit(p, s, quartets, n_quartets);
     } catch (const std::bad_alloc&) {
         rc = ERI_ENOMEM;
@@ -695,7 +608,7 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
 {
     const int64_t n = p->class_count[c];
     if (n == 0) return ERI_OK;
-    const eri_kernel_info& ki = kernel_table(p->precision)[c];
+    const eri_kernel_info& ki = kernel_table(p->precision)[class_id5_of(c)];
     eri_class_args a;
     fill_args(p, c, a, out_eri, out_codes, out_scales);
     if (!p->batched) {

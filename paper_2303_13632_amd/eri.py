@@ -80,6 +80,7 @@ def load():
     lib.eri_compute_class.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
     lib.eri_compress.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
     lib.eri_decompress.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.eri_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eri_plan_destroy.argtypes = [_vp]
     lib.eri_plan_destroy.restype = None
     lib.eri_status_string.argtypes = [ctypes.c_int]
@@ -220,6 +221,48 @@ class Plan:
         _check(load().eri_compute_class(self._h, int(cid), _stream(stream), _ptr(out_eri), _ptr(out_codes),
                                         _ptr(out_scales)), "eri_compute_class")
 
+    @property
+    def n_prims(self):
+        """Length of the exponent array (gradients per primitive)."""
+        return len(self.shells["exps"])
+
+    @property
+    def nbf(self):
+        """Cartesian basis functions of the shell set."""
+        return int(sum(_ncart(l) for l in self.shells["L"]))
+
+    def backward(self, dl=None, density=None, grad_centers=None, grad_exps=None, energy=None, stream=None):
+        """eri_backward: adds dL/dxyz and dL/dexps of L = sum w Gbar (ab|cd)
+        (Gbar = dl in the plan layout, or D D from a density) into the given
+        device tensors, allocating zeroed ones when None.  Returns
+        (grad_centers [n_shells, 3], grad_exps [n_prims], energy [1])."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if grad_centers is None:
+            grad_centers = torch.zeros((len(self.shells["L"]), 3), dtype=torch.float64, device=dev)
+        if grad_exps is None:
+            grad_exps = torch.zeros(max(self.n_prims, 1), dtype=torch.float64, device=dev)
+        if energy is None:
+            energy = torch.zeros(1, dtype=torch.float64, device=dev)
+        for t in (dl, density, grad_centers, grad_exps, energy):
+            if t is not None and (t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError("eri_backward takes contiguous float64 device tensors")
+        if dl is not None and dl.numel() < self.out_values:
+            raise ValueError("dl holds %d values, the plan layout %d" % (dl.numel(), self.out_values))
+        nbf = 0 if density is None else int(density.shape[0])
+        _check(load().eri_backward(self._h, _stream(stream), _ptr(dl), _ptr(density), nbf, _ptr(grad_centers),
+                                   _ptr(grad_exps), _ptr(energy)), "eri_backward")
+        return grad_centers, grad_exps[: self.n_prims], energy
+
+    def check_parameters(self, centers, exps):
+        """The plan's integrals are those of its shell set: autograd inputs
+        must hold the same centres and exponents."""
+        c = centers.detach().to("cpu", torch_float64()).numpy().reshape(-1, 3)
+        e = exps.detach().to("cpu", torch_float64()).numpy().reshape(-1)
+        if not (np.array_equal(c, np.asarray(self.shells["xyz"], dtype=np.float64).reshape(-1, 3)) and
+                np.array_equal(e, np.asarray(self.shells["exps"], dtype=np.float64))):
+            raise ValueError("centres/exponents differ from the plan's shell set; build a new plan")
+
     def to_user(self, values):
         """Plan-order per-ERI array (numpy) -> user order (concatenated blocks)."""
         pos, eoff = self.layout()
@@ -271,3 +314,63 @@ def decompress(bits, codes, scales, block_off, out=None, stream=None):
     _check(load().eri_decompress(int(bits), _ptr(codes), _ptr(scales), nb, _ptr(block_off), _ptr(out),
                                  _stream(stream)), "eri_decompress")
     return out
+
+
+def torch_float64():
+    import torch
+    return torch.float64
+
+
+def _make_autograd():
+    import torch
+
+    class ERIFunction(torch.autograd.Function):
+        """values = ERIFunction.apply(centers, exps, plan): the plan's FP64 ERIs
+        (plan layout) as a differentiable function of the shell centres
+        [n_shells, 3] and primitive exponents; backward calls eri_backward."""
+
+        @staticmethod
+        def forward(ctx, centers, exps, plan):
+            plan.check_parameters(centers, exps)
+            out, _, _ = plan.alloc(eri=True, codes=False)
+            plan.compute(out)
+            ctx.plan = plan
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            plan = ctx.plan
+            gc, ge, _ = plan.backward(dl=g.to(torch.float64).contiguous())
+            return gc, ge, None
+
+    class CoulombEnergy(torch.autograd.Function):
+        """E = CoulombEnergy.apply(centers, exps, plan, density): the density
+        contraction sum D D (ab|cd) over the plan's quartets (weighted by their
+        degeneracy for all-quartet plans), computed together with its
+        gradient in one eri_backward call."""
+
+        @staticmethod
+        def forward(ctx, centers, exps, plan, density):
+            plan.check_parameters(centers, exps)
+            gc, ge, en = plan.backward(density=density.to(torch.float64).contiguous())
+            ctx.save_for_backward(gc, ge)
+            return en[0].clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            gc, ge = ctx.saved_tensors
+            return g * gc, g * ge, None, None
+
+    return ERIFunction, CoulombEnergy
+
+
+_autograd = None
+
+
+def __getattr__(name):
+    global _autograd
+    if name in ("ERIFunction", "CoulombEnergy"):
+        if _autograd is None:
+            _autograd = _make_autograd()
+        return _autograd[0] if name == "ERIFunction" else _autograd[1]
+    raise AttributeError(name)

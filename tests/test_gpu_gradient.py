@@ -1,0 +1,182 @@
+"""GPU tests of the adjoint (eri_backward): gradients with respect to shell
+centres and primitive exponents against the oracle's analytic gradient (all
+four centres differentiated explicitly there), against finite differences of
+the GPU forward values, and through the autograd functions."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2303_13632_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+RTOL = 1e-10     # relative to the largest gradient entry
+
+
+def _quartets(n_shells, n, seed):
+    rng = np.random.default_rng(seed)
+    q = rng.integers(0, n_shells, size=(n, 4)).astype(np.int32)
+    q[:4] = [[0, 0, 1, 1], [2, 3, 2, 3], [4, 4, 4, 4], [1, 0, 0, 1]]
+    return q
+
+
+def _close(got, ref, tol=RTOL):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(got - ref).max()
+    assert err <= tol * scale, (err, scale)
+
+
+def _dl_plan(plan, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=plan.out_values)
+
+
+@pytest.mark.parametrize("seed", [101, 102])
+def test_explicit_dl_vs_oracle(seed):
+    """Random dL/dERI over a quartet list that covers s, p, d shells in every
+    position (repeated shells, swapped orders): GPU vs oracle gradient."""
+    from paper_2303_13632_amd import eri
+    print("explicit dl seed", seed, flush=True)
+    sh = W.random_shells(12, lmax=2, seed=seed, box=4.0)
+    q = _quartets(12, 300, seed)
+    plan = eri.Plan(sh, q, bits=0)
+    dlp = _dl_plan(plan, seed)
+    dl_t = torch.tensor(dlp, device="cuda")
+    gc, ge, en = plan.backward(dl=dl_t, energy=None)
+    torch.cuda.synchronize()
+    E, gx, gex = O.gradient(sh, q, dl=plan.to_user(dlp), n_threads=THREADS)
+    _close(gc.cpu().numpy(), gx)
+    _close(ge.cpu().numpy(), gex)
+    assert abs(en.item() - E) <= RTOL * abs(E)
+
+
+def test_explicit_density_vs_oracle():
+    from paper_2303_13632_amd import eri
+    sh = W.random_shells(10, lmax=2, seed=111, box=4.0)
+    q = _quartets(10, 200, 111)
+    plan = eri.Plan(sh, q, bits=0)
+    D = W.random_density(plan.nbf, seed=111)
+    gc, ge, en = plan.backward(density=torch.tensor(D, device="cuda"))
+    torch.cuda.synchronize()
+    E, gx, gex = O.gradient(sh, q, density=D, n_threads=THREADS)
+    _close(gc.cpu().numpy(), gx)
+    _close(ge.cpu().numpy(), gex)
+    assert abs(en.item() - E) <= RTOL * abs(E)
+
+
+def _unique_weights(qs):
+    w = np.ones(len(qs))
+    w *= np.where(qs[:, 0] != qs[:, 1], 2.0, 1.0)
+    w *= np.where(qs[:, 2] != qs[:, 3], 2.0, 1.0)
+    same = (np.minimum(qs[:, 0], qs[:, 1]) == np.minimum(qs[:, 2], qs[:, 3])) & \
+           (np.maximum(qs[:, 0], qs[:, 1]) == np.maximum(qs[:, 2], qs[:, 3]))
+    w *= np.where(same, 1.0, 2.0)
+    return w
+
+
+def test_batched_density_vs_oracle():
+    """All unique screened quartets of a small molecule-like basis, density
+    form with degeneracy weights: E and gradient against the oracle over the
+    same quartets."""
+    from paper_2303_13632_amd import eri
+    sh = W.molecule_basis(n_heavy=1, n_h=3, lattice=(2, 2, 1), seed=W.SEED_BASE + 44)
+    plan = eri.Plan(sh, None, bits=16, schwarz=1e-10)
+    D = W.random_density(plan.nbf, seed=44)
+    gc, ge, en = plan.backward(density=torch.tensor(D, device="cuda"))
+    torch.cuda.synchronize()
+    qs = np.concatenate([plan.class_quartet_list(c) for c in range(256) if plan.class_quartets[c]])
+    print("batched quartets", len(qs), flush=True)
+    E, gx, gex = O.gradient(sh, qs, weights=_unique_weights(qs), density=D, n_threads=THREADS)
+    _close(gc.cpu().numpy(), gx)
+    _close(ge.cpu().numpy(), gex)
+    assert abs(en.item() - E) <= RTOL * abs(E)
+
+
+def test_gradient_vs_gpu_finite_differences():
+    """Central differences (Richardson, h = 1e-3) of the GPU forward values
+    contracted with a fixed dL/dERI, on a sample of coordinates and
+    exponents."""
+    from paper_2303_13632_amd import eri
+    sh = W.random_shells(8, lmax=2, seed=121, box=3.0)
+    q = _quartets(8, 120, 121)
+    plan = eri.Plan(sh, q, bits=0)
+    dlp = _dl_plan(plan, 121)
+    gc, ge, _ = plan.backward(dl=torch.tensor(dlp, device="cuda"))
+    gc, ge = gc.cpu().numpy(), ge.cpu().numpy()
+    scale = max(np.abs(gc).max(), np.abs(ge).max())
+
+    def energy(s2):
+        p2 = eri.Plan(s2, q, bits=0)
+        out, _, _ = p2.alloc(eri=True, codes=False)
+        p2.compute(out)
+        torch.cuda.synchronize()
+        return float(np.dot(out.cpu().numpy()[: p2.out_values], dlp))
+
+    def fd(key, idx, h):
+        def at(d):
+            s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
+            s2[key].reshape(-1)[idx] += d
+            return energy(s2)
+        d1 = (at(h) - at(-h)) / (2 * h)
+        d2 = (at(h / 2) - at(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    rng = np.random.default_rng(121)
+    for idx in rng.choice(3 * 8, size=6, replace=False):
+        v = fd("xyz", int(idx), 1e-3)
+        assert abs(v - gc.reshape(-1)[idx]) <= 1e-7 * scale, ("xyz", idx, v, gc.reshape(-1)[idx])
+    for idx in rng.choice(len(sh["exps"]), size=6, replace=False):
+        v = fd("exps", int(idx), 1e-3 * sh["exps"][idx])
+        assert abs(v - ge[idx]) <= 1e-7 * scale, ("exps", idx, v, ge[idx])
+
+
+def test_autograd_functions():
+    from paper_2303_13632_amd import eri
+    sh = W.random_shells(6, lmax=2, seed=131, box=3.0)
+    q = _quartets(6, 60, 131)
+    plan = eri.Plan(sh, q, bits=0)
+    c = torch.tensor(sh["xyz"], device="cuda", requires_grad=True)
+    e = torch.tensor(sh["exps"], device="cuda", requires_grad=True)
+    vals = eri.ERIFunction.apply(c, e, plan)
+    w = torch.tensor(_dl_plan(plan, 131), device="cuda")
+    (vals[: plan.out_values] * w).sum().backward()
+    gc, ge, _ = plan.backward(dl=w)
+    torch.cuda.synchronize()
+    _close(c.grad.cpu().numpy(), gc.cpu().numpy(), 1e-13)
+    _close(e.grad.cpu().numpy(), ge.cpu().numpy(), 1e-13)
+    # energy form
+    D = torch.tensor(W.random_density(plan.nbf, seed=131), device="cuda")
+    c.grad = None
+    e.grad = None
+    E = eri.CoulombEnergy.apply(c, e, plan, D)
+    (3.0 * E).backward()
+    E0, gx, gex = O.gradient(sh, q, density=D.cpu().numpy(), n_threads=THREADS)
+    assert abs(E.item() - E0) <= RTOL * abs(E0)
+    _close(c.grad.cpu().numpy(), 3.0 * gx)
+    _close(e.grad.cpu().numpy(), 3.0 * gex)
+
+
+def test_errors_and_empty():
+    from paper_2303_13632_amd import eri
+    sh = W.random_shells(4, lmax=2, seed=141)
+    empty = eri.Plan(sh, np.zeros((0, 4), np.int32), bits=0)
+    gc, ge, en = empty.backward(dl=torch.zeros(1, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert not gc.any() and not ge.any() and en.item() == 0.0
+    f = W.random_shells(4, lmax=3, seed=142)
+    f["L"][:] = 3
+    pf = eri.Plan(f, np.array([[0, 1, 2, 3]], np.int32), bits=0)
+    with pytest.raises(eri.EriError) as ex:
+        pf.backward(dl=torch.zeros(pf.out_values, dtype=torch.float64, device="cuda"))
+    assert ex.value.status == eri.ERI_EUNSUPPORTED
+    mol = W.molecule_basis(n_heavy=1, n_h=2, lattice=(2, 2, 1), seed=W.SEED_BASE + 45)
+    ring = eri.Plan(mol, None, bits=16, ring_bytes=4096)
+    assert np.any(ring.class_ring < ring.class_quartets)
+    with pytest.raises(eri.EriError) as ex:
+        ring.backward(dl=torch.zeros(ring.out_values, dtype=torch.float64, device="cuda"))
+    assert ex.value.status == eri.ERI_ESTATE
+    with pytest.raises(eri.EriError):
+        ring.backward(density=torch.zeros((ring.nbf + 1, ring.nbf + 1), dtype=torch.float64, device="cuda"))
