@@ -72,9 +72,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
-    ap.add_argument("--workload", default="classes", choices=["classes", "molecule"],
+    ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
-                         "unique quartet of the 384-atom molecule-like basis in one graph launch")
+                         "unique quartet of the 384-atom molecule-like basis in one graph launch; "
+                         "gradient: E = sum D D (ab|cd) and its gradient on the 64-atom basis")
     ap.add_argument("--molecule-scale", type=float, default=1.0, help="fraction of the molecule's atoms")
     ap.add_argument("--schwarz", type=float, default=1e-10)
     ap.add_argument("--ring-gb", type=float, default=48.0)
@@ -90,6 +91,8 @@ def main():
 
     if args.workload == "molecule":
         return bench_molecule(args)
+    if args.workload == "gradient":
+        return bench_gradient(args)
     classes = list(range(256)) if args.classes == "all" else [int(c) for c in args.classes.split(",")]
     t0 = time.time()
     shells, quartets = build_workload(args.quartets_per_class, classes)
@@ -209,6 +212,72 @@ def bench_molecule(args):
                    "n_shells": int(len(sh["L"])), "n_quartets": int(plan.n_quartets),
                    "n_eri": int(plan.n_eri), "n_prim_quartets": int(plan.n_prim_quartets)},
         "whole_step_tflops": flops / (ms_step / 1e3) / 1e12,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_gradient(args):
+    """Forward + adjoint on the 64-atom basis (22 heavy + 42 H on a 4x4x4
+    lattice, s-d shells): every unique Schwarz-screened quartet computed with
+    int16 codes (one graph launch), then E = sum D D (ab|cd) with the
+    gradient for all centres and exponents (eri_backward, density form)."""
+    import torch
+    from paper_2303_13632_amd import eri, workloads as W
+    sh = W.gradient_basis()
+    t0 = time.time()
+    plan = eri.Plan(sh, None, precision="fp64", bits=args.bits, schwarz=args.schwarz)
+    D = torch.tensor(W.random_density(plan.nbf), device="cuda")
+    log("plan: %d shells, %d basis functions, %d screened quartets, %d ERIs (%.1fs)"
+        % (len(sh["L"]), plan.nbf, plan.n_quartets, plan.n_eri, time.time() - t0))
+    _, codes, scales = plan.alloc(eri=False, codes=True)
+    gc = torch.zeros((len(sh["L"]), 3), dtype=torch.float64, device="cuda")
+    ge = torch.zeros(plan.n_prims, dtype=torch.float64, device="cuda")
+    en = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        plan.compute(None, codes, scales, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        gc.zero_()
+        ge.zero_()
+        en.zero_()
+        if ev:
+            ev[2].record(stream)
+        plan.backward(density=D, grad_centers=gc, grad_exps=ge, energy=en, stream=stream)
+        if ev:
+            ev[3].record(stream)
+
+    t0 = time.time()
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    log("warmup (incl. derived tables) %.1fs" % (time.time() - t0))
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+        log("step %d done" % k)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    bwd = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
+    ms_step = wall * 1e3 / args.steps
+    out = {
+        "metric": METRIC, "value": plan.n_eri / (ms_step / 1e3) / 1e9, "unit": "GERIS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "adjoint: 64-atom basis (22 heavy s,s,s,p,p,d K 1-6 + 42 H s,s,p; 4x4x4 jittered "
+                               "3.5 Bohr lattice), all unique quartets with Q_ab Q_cd >= %g; forward with int%d "
+                               "codes, then E = sum D D (ab|cd), D symmetric N(0, 0.1), and dE/d(centres, "
+                               "exponents)" % (args.schwarz, args.bits),
+                   "n_shells": int(len(sh["L"])), "n_quartets": int(plan.n_quartets), "n_eri": int(plan.n_eri)},
+        "forward_ms": fwd, "adjoint_ms": bwd,
+        "forward_geris": plan.n_eri / (fwd / 1e3) / 1e9, "adjoint_geris": plan.n_eri / (bwd / 1e3) / 1e9,
+        "energy": float(en.item()), "grad_centres_norm": float(gc.norm().item()),
+        "grad_exps_norm": float(ge.norm().item()),
     }
     print(json.dumps(out), flush=True)
 

@@ -91,6 +91,11 @@ typedef struct {
     int64_t class_eri_off[257];   /* first ERI of each class in plan order */
     int64_t class_quartet_off[257];
     double class_flops[256];      /* algorithmic FLOPs of each class launch */
+    int32_t class_variant[256];   /* launch variant in use (0 = default; see eri_plan_tune) */
+    int32_t class_mode[256];      /* its work mapping: 0 = one lane per quartet, 1 = a slot of lanes */
+    int32_t class_block[256];     /* its threads per workgroup */
+    int32_t class_per_block[256]; /* its quartets per workgroup */
+    int32_t class_n_variants[256];/* launch variants available: 0 .. n-1 */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
@@ -146,6 +151,29 @@ int eri_compute(eri_plan* plan, void* stream, double* out_eri, void* out_codes, 
 int eri_compute_class(eri_plan* plan, int32_t class_id, void* stream, double* out_eri,
                       void* out_codes, double* out_scales);
 
+/* Autotuner for the class launches (work mapping and quartets per
+ * workgroup).  Each class may have several launch variants: the generated
+ * mapping at 64, 128 or 256 quartets per workgroup (one lane per quartet),
+ * and an alternate mapping (a slot of lanes per quartet instead of one lane,
+ * or the reverse).  For every class of the plan with more than one variant,
+ * the first min(class_quartets, sample_quartets) quartets are computed with
+ * each variant `trials` times on `stream` (outputs to scratch memory the call
+ * allocates and frees; the plan's codes width is kept) and the fastest mean
+ * time wins.  With cache_path, choices stored there under the key
+ * "<precision>:<class id>:<bits>" are used without timing, and the file is
+ * rewritten with every choice made.  Synchronises the stream; invalidates the
+ * captured graph of ERI_PLAN_ALL_QUARTETS plans.  All variants of a class
+ * compute the same integrals in the same orientation and layout; their
+ * values may differ in the last bits (other operation order).
+ * Returns ERI_EINVAL for sample_quartets < 1 or trials < 1, ERI_EHIP /
+ * ERI_ENOMEM on device failures; an unreadable cache file is ignored and an
+ * unwritable one returns ERI_EINVAL after the tuning is applied. */
+int eri_plan_tune(eri_plan* plan, void* stream, int64_t sample_quartets, int32_t trials, const char* cache_path);
+
+/* Set the launch variant of every class (256 entries, 0 = default).
+ * ERI_EINVAL if a class has no such variant. */
+int eri_plan_set_variants(eri_plan* plan, const int32_t* variants);
+
 /* Standalone compression (eqs. 9-10) of FP64 values on the device: block b is
  * eri[block_off[b] .. block_off[b+1]) and gets scale scales[b] and codes in the
  * same positions.  block_off: device int64, n_blocks + 1 entries.
@@ -169,7 +197,9 @@ int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_
  * Exactly one of dl_deri and density is given.  The call ADDS dL/dR to
  * grad_centers (device, 3 per shell, the shell's centre xyz) and dL/dalpha to
  * grad_exps (device, one per primitive, indexed like exps: prim_off[s] + k),
- * and L itself to *energy (device, optional).  The coefficients are constants.
+ * and L itself to *energy (device, optional).  With grad_centers and grad_exps
+ * both NULL only L is computed (energy then required).  The coefficients are
+ * constants.
  * Derivatives follow from the differentiated Gaussians (centre: 2 alpha
  * g(a+1) - a g(a-1); exponent: N[(3/4 + L/2)/alpha g(a) - sum g(a+2)]) as
  * contracted ERIs of derived shells computed by the FP64 class kernels,

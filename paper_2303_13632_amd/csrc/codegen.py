@@ -84,16 +84,20 @@ def class_id5(la, lb, lc, ld):
     return la * 125 + lb * 25 + lc * 5 + ld
 
 
-def kernel_name(prec, user):
+def kernel_name(prec, user, alt=False):
     """eri_<prec>_cNNN for s-f classes (NNN = La*64+Lb*16+Lc*4+Ld), eri_<prec>_gNNN
-    (NNN = La*125+Lb*25+Lc*5+Ld) for classes with a g shell (derivative shells)."""
+    (NNN = La*125+Lb*25+Lc*5+Ld) for classes with a g shell (derivative shells);
+    suffix _a for the alternate-mode kernel of a class."""
+    suf = "_a" if alt else ""
     if max(user) <= 3:
-        return "eri_%s_c%03d" % (prec, class_id(*user))
-    return "eri_%s_g%03d" % (prec, class_id5(*user))
+        return "eri_%s_c%03d%s" % (prec, class_id(*user), suf)
+    return "eri_%s_g%03d%s" % (prec, class_id5(*user), suf)
 
 
 # classes with one g shell and s, p, d on the others: the exponent derivatives
 # of d shells (L + 2) in the adjoint
+MAXVAR = 6   # launch variants per class (ERI_MAXVAR)
+
 G_CLASSES = [c for c in itertools.product(range(5), repeat=4) if sorted(c)[-1] == 4 and sorted(c)[-2] <= 2]
 
 
@@ -338,16 +342,15 @@ def hrr_expr(b, a, getter, prefix):
 # ---------------------------------------------------------------------------
 # Mode T kernel
 # ---------------------------------------------------------------------------
-def emit_mode_T(cp, prec):
+def emit_mode_T(cp, prec, name):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
-    name = kernel_name(prec, cp.user)
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode T, %s" % (cp.user + (cp.perm, a, b, c, d, prec)))
-    em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
+    em("__global__ __launch_bounds__(256) void %s(eri_class_args A)" % name)
     em.block("")
-    em("const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;")
+    em("const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;")
     em("if (t >= A.n_items) return;")
     em("const eri_item it = A.items[t];")
     em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
@@ -502,11 +505,10 @@ def wave_layout(cp):
     return subs, ep
 
 
-def emit_mode_W(cp, prec, lds_budget=32768):
+def emit_mode_W(cp, prec, name, lds_budget=32768):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
-    name = kernel_name(prec, cp.user)
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     subs, EP = wave_layout(cp)
     S = len(subs)
@@ -537,7 +539,7 @@ def emit_mode_W(cp, prec, lds_budget=32768):
             else:
                 row += [0, 0, 0, 0, -1, ls, ls, ls]
         rows.append(row)
-    tbl = "eri_tbl_" + kernel_name(prec, cp.user)[4:]
+    tbl = "eri_tbl_" + name[4:]
     em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode W: %d lanes/slot, %d slot(s), %d subslot(s), %s"
        % (cp.user + (cp.perm, a, b, c, d, EP, NSLOT, S, prec)))
     em("static __constant__ signed char %s[%d][%d] = {" % (tbl, EP, 8 * S))
@@ -546,7 +548,12 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     em("};")
     em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
     em.block("")
-    em("__shared__ double s_t[%d][%d][%d];" % (NSLOT, NTE, CH))
+    NF = cp.Ltot + 1 + 17          # staged fields of one primitive quartet
+    NSU = max(NSLOT * NTE * CH, NF * 64)
+    # one LDS buffer: primitive-quartet staging during the VRR loop, then the
+    # HRR staging s_t[slot][target e][cd chunk]
+    em("__shared__ double s_u[%d];" % NSU)
+    em("double (*s_t)[%d][%d] = reinterpret_cast<double (*)[%d][%d]>(s_u);" % (NTE, CH, NTE, CH))
     em("__shared__ double s_red[64];")
     em("const int lane = threadIdx.x;")
     em("const int slot = lane / %d;" % EP)
@@ -560,36 +567,70 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     em("const int nbra = active ? BP.nprim : 0;")
     em("const int nket = KP.nprim;")
     em("const int sbase = slot * %d;" % EP)
-    for s in range(S):
+    # lanes of an unused tail slot read the first slot's staging (never stored)
+    em("const int pbase = slot < %d ? sbase : 0;" % NSLOT)
+    for s_ in range(S):
         em("const int ex%d = %s[ls][%d], ey%d = %s[ls][%d], ez%d = %s[ls][%d];"
-           % (s, tbl, 8 * s, s, tbl, 8 * s + 1, s, tbl, 8 * s + 2))
-        em("const int tg%d = %s[ls][%d];" % (s, tbl, 8 * s + 4))
+           % (s_, tbl, 8 * s_, s_, tbl, 8 * s_ + 1, s_, tbl, 8 * s_ + 2))
+        em("const int tg%d = %s[ls][%d];" % (s_, tbl, 8 * s_ + 4))
         em("const int sx%d = sbase + %s[ls][%d], sy%d = sbase + %s[ls][%d], sz%d = sbase + %s[ls][%d];"
-           % (s, tbl, 8 * s + 5, s, tbl, 8 * s + 6, s, tbl, 8 * s + 7))
+           % (s_, tbl, 8 * s_ + 5, s_, tbl, 8 * s_ + 6, s_, tbl, 8 * s_ + 7))
     # accumulators per subslot
     acc = {}
-    for s in range(S):
+    for s_ in range(S):
         for f in cp.F_T:
-            acc[(s, f)] = "acc%d_%d%d%d" % ((s,) + f)
-            em("double %s = 0.0;" % acc[(s, f)])
-    em.block("for (int ib = 0; ib < nbra; ++ib)")
+            acc[(s_, f)] = "acc%d_%d%d%d" % ((s_,) + f)
+            em("double %s = 0.0;" % acc[(s_, f)])
+    # Primitive quartets go through the slot in batches of EP: lane ls does
+    # the setup and Boys evaluation of quartet j0 + ls once and stages the
+    # results in LDS; then every lane runs the recurrences of each staged
+    # quartet.  Trip counts are wave-uniform (max over the slots), staged
+    # entries past a slot's own count are zero and contribute nothing.
+    em("const int npq = nbra * nket;")
+    em("int npq_w = npq;")
+    em("for (int o = 32; o > 0; o >>= 1) npq_w = max(npq_w, __shfl_xor(npq_w, o));")
+    em.block("for (int j0 = 0; j0 < npq_w; j0 += %d)" % EP)
+    em("__syncthreads();")
+    em.block("")
+    em("double g[%d];" % NF)
+    em("#pragma unroll")
+    em("for (int q = 0; q < %d; ++q) g[q] = 0.0;" % NF)
+    em("const int j = j0 + ls;")
+    em.block("if (active && j < npq)")
+    em("const int ib = j / nket, ik = j - ib * nket;")
     em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
-    em.block("for (int ik = 0; ik < nket; ++ik)")
     em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
     em("eri_pq_fp64 S;")
     em("eri_pq_setup(B, K, S);")
     em("double F[%d];" % (cp.Ltot + 1))
     em("eri_boys<%d>(S.T, F);" % cp.Ltot)
-    em("const %s QCx = (%s)K.PA[0], QCy = (%s)K.PA[1], QCz = (%s)K.PA[2];" % ((real,) * 4))
-    em("const %s WQx = (%s)S.WQ[0], WQy = (%s)S.WQ[1], WQz = (%s)S.WQ[2];" % ((real,) * 4))
-    em("const %s hp = (%s)B.hp, hq = (%s)K.hp, hpq = (%s)S.hpq, rp = (%s)S.rho_p, rq = (%s)S.rho_q;" % ((real,) * 6))
+    em("#pragma unroll")
+    em("for (int m = 0; m <= %d; ++m) g[m] = S.pref * F[m];" % cp.Ltot)
+    o = cp.Ltot + 1
+    fields = ["B.PA[0]", "B.PA[1]", "B.PA[2]", "S.WP[0]", "S.WP[1]", "S.WP[2]",
+              "K.PA[0]", "K.PA[1]", "K.PA[2]", "S.WQ[0]", "S.WQ[1]", "S.WQ[2]",
+              "B.hp", "K.hp", "S.hpq", "S.rho_p", "S.rho_q"]
+    for k, fld in enumerate(fields):
+        em("g[%d] = %s;" % (o + k, fld))
+    em.end()
+    em("#pragma unroll")
+    em("for (int q = 0; q < %d; ++q) s_u[q * 64 + lane] = g[q];" % NF)
+    em.end()
+    em("__syncthreads();")
+    em("const int nb = min(%d, npq_w - j0);" % EP)
+    em.block("for (int jj = 0; jj < nb; ++jj)")
+    em("const double* u = s_u + pbase + jj;")
+    names = ["PAx", "PAy", "PAz", "WPx", "WPy", "WPz", "QCx", "QCy", "QCz", "WQx", "WQy", "WQz",
+             "hp", "hq", "hpq", "rp", "rq"]
+    for k, nm in enumerate(names):
+        em("const %s %s = (%s)u[%d];" % (real, nm, real, 64 * (o + k)))
     MB = cp.Ltot
-    for s in range(S):
-        em("%s c%d[%d], p%d[%d], nx%d[%d];" % (real, s, MB + 2, s, MB + 2, s, MB + 2))
+    for s_ in range(S):
+        em("%s c%d[%d], p%d[%d], nx%d[%d];" % (real, s_, MB + 2, s_, MB + 2, s_, MB + 2))
         em("#pragma unroll")
-        em("for (int m = 0; m <= %d; ++m) { c%d[m] = (%s)(S.pref * F[m]); p%d[m] = (%s)0; }" % (MB, s, real, s, real))
+        em("for (int m = 0; m <= %d; ++m) { c%d[m] = (%s)u[64 * m]; p%d[m] = (%s)0; }" % (MB, s_, real, s_, real))
         em("const %s cex%d = (%s)ex%d * hpq, cey%d = (%s)ey%d * hpq, cez%d = (%s)ez%d * hpq;"
-           % (real, s, real, s, s, real, s, s, real, s))
+           % (real, s_, real, s_, s_, real, s_, s_, real, s_))
     # bra path: step t builds level t along z, then y, then x; lanes already
     # at their |e| apply the identity (pa = 1, wp = 0, c = 0).
     for s in range(S):
@@ -600,8 +641,8 @@ def emit_mode_W(cp, prec, lds_budget=32768):
             em("const bool iy = !iz && %d <= ez%d + ey%d;" % (t, s, s))
             em("const bool ix = !iz && !iy && %d <= ez%d + ey%d + ex%d;" % (t, s, s, s))
             em("const int nt = iz ? %d : iy ? %d - ez%d : ix ? %d - ez%d - ey%d : 0;" % (t - 1, t - 1, s, t - 1, s, s))
-            em("const %s pa = iz ? (%s)B.PA[2] : iy ? (%s)B.PA[1] : ix ? (%s)B.PA[0] : (%s)1;" % ((real,) * 5))
-            em("const %s wp = iz ? (%s)S.WP[2] : iy ? (%s)S.WP[1] : ix ? (%s)S.WP[0] : (%s)0;" % ((real,) * 5))
+            em("const %s pa = iz ? PAz : iy ? PAy : ix ? PAx : (%s)1;" % (real, real))
+            em("const %s wp = iz ? WPz : iy ? WPy : ix ? WPx : (%s)0;" % (real, real))
             em("const %s cc = (%s)nt * hp;" % (real, real))
             em("#pragma unroll")
             em("for (int m = 0; m <= %d; ++m) nx%d[m] = pa * c%d[m] + wp * c%d[m + 1] + cc * (p%d[m] - rp * p%d[m + 1]);"
@@ -722,10 +763,22 @@ def emit_mode_W(cp, prec, lds_budget=32768):
     return name, em.text()
 
 
-def emit_class(cp, prec):
+def emit_class(cp, prec, alt=False):
+    name = kernel_name(prec, cp.user, alt)
     if cp.mode == "T":
-        return emit_mode_T(cp, prec)
-    return emit_mode_W(cp, prec)
+        return name, emit_mode_T(cp, prec, name)[1]
+    return name, emit_mode_W(cp, prec, name)[1]
+
+
+def alternate_mode(cp):
+    """The other work mapping, where it is worth a timed trial: lane per
+    quartet for mid-size classes mapped to slots, slots for the larger
+    classes mapped to one lane per quartet."""
+    if cp.mode == "W" and cp.n_eriq <= 144 and len(cp.elems) <= 320:
+        return "T"
+    if cp.mode == "T" and cp.Ltot >= 3:
+        return "W"
+    return None
 
 
 HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
@@ -733,13 +786,21 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 """
 
 
-def kernel_info_init(cp, name):
+def kernel_info_init(cp, name, block=64):
     subs, EP = wave_layout(cp)
     per_pq, per_q = cp.flops()
     pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
     if cp.mode == "T":
-        return "{(const void*)%s, 0, 64, 64, %d, %d, %d, %d, 0}" % (name, cp.n_eriq, per_pq, per_q, pk)
+        return "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, 0}" % (name, block, block, cp.n_eriq, per_pq, per_q, pk)
     return "{(const void*)%s, 1, 64, %d, %d, %d, %d, %d, 0}" % (name, 64 // EP, cp.n_eriq, per_pq, per_q, pk)
+
+
+def variant_infos(cp, name):
+    """Launch variants of one kernel: mode T at 64, 128 and 256 quartets per
+    workgroup, mode W as generated."""
+    if cp.mode == "T":
+        return [kernel_info_init(cp, name, b) for b in (64, 128, 256)]
+    return [kernel_info_init(cp, name)]
 
 
 def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None, g_classes=True):
@@ -769,26 +830,47 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 plans[user] = cp
             name, src = emit_class(cp, prec)
             parts.append(src)
-            reg.setdefault(prec, []).append("    t[%d] = %s;" % (class_id5(*user), kernel_info_init(cp, name)))
+            c5 = class_id5(*user)
+            lines_ = reg.setdefault(prec, [])
+            lines_.append("    t[%d] = %s;" % (c5, kernel_info_init(cp, name)))
+            infos = variant_infos(cp, name)
+            am = alternate_mode(cp) if max(user) <= 3 else None
+            if am is not None:
+                acp = ClassPlan(*user, mode=am, perm=cp.perm)
+                aname, asrc = emit_class(acp, prec, alt=True)
+                parts.append(asrc)
+                infos += variant_infos(acp, aname)
+            for k, info in enumerate(infos):
+                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
         for prec, lines_ in reg.items():
             fname = "eri_register_%s_g%03d" % (prec, g // group)
-            parts.append("void %s(eri_kernel_info* t)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
+            parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
             regs.append((prec, fname))
         fn = os.path.join(outdir, "eri_k%03d.hip" % (g // group))
         write_if_changed(fn, "\n".join(parts))
         files.append(fn)
     lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
     for prec, fname in regs:
-        lines.append("void %s(eri_kernel_info* t);" % fname)
+        lines.append("void %s(eri_kernel_info* t, eri_kernel_info* v);" % fname)
     lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5];")
+    lines.append("static eri_kernel_info v_fp64[ERI_NCLASS5 * ERI_MAXVAR], v_mixed[ERI_NCLASS5 * ERI_MAXVAR];")
     lines.append("static std::once_flag g_once;")
-    lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
+    lines.append("static void fill()")
     lines.append("{")
     lines.append("    std::call_once(g_once, [] {")
     for prec, fname in regs:
-        lines.append("        %s(%s);" % (fname, "g_fp64" if prec == "fp64" else "g_mixed"))
+        lines.append("        %s(%s);" % (fname, "g_fp64, v_fp64" if prec == "fp64" else "g_mixed, v_mixed"))
     lines.append("    });")
+    lines.append("}")
+    lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
+    lines.append("{")
+    lines.append("    fill();")
     lines.append("    return precision == 1 ? g_mixed : g_fp64;")
+    lines.append("}")
+    lines.append("const eri_kernel_info* eri_kernel_variants(int precision)")
+    lines.append("{")
+    lines.append("    fill();")
+    lines.append("    return precision == 1 ? v_mixed : v_fp64;")
     lines.append("}")
     fn = os.path.join(outdir, "eri_dispatch_table.hip")
     write_if_changed(fn, "\n".join(lines) + "\n")

@@ -457,11 +457,11 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const dou
     const eri_kernel_info* tab = kernel_table(ERI_FP64);
     std::vector<bwd_kind> kinds;
     if (energy) kinds.push_back({0, DK_BASE, 0});
-    for (int x = 0; x < 3; ++x) {
+    for (int x = 0; x < 3 && grad_c; ++x) {
         kinds.push_back({x, DK_PLUS, 0});
         if (L[x] >= 1) kinds.push_back({x, DK_MINUS, 0});
     }
-    for (int x = 0; x < 4; ++x)
+    for (int x = 0; x < 4 && grad_c; ++x)
         for (int k = 0; k < st->kmax[L[x]]; ++k) {
             kinds.push_back({x, DK_E0, k});
             kinds.push_back({x, DK_E2, k});
@@ -551,7 +551,8 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const dou
 extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, const double* density, int64_t nbf,
                             double* grad_centers, double* grad_exps, double* energy)
 {
-    if (!p || !grad_centers || !grad_exps) return ERI_EINVAL;
+    if (!p || (grad_centers == nullptr) != (grad_exps == nullptr)) return ERI_EINVAL;
+    if (!grad_centers && !energy) return ERI_EINVAL;
     if ((dl_deri == nullptr) == (density == nullptr)) return ERI_EINVAL;
     for (int32_t l : p->sh_L)
         if (l > BWD_MAXL) return ERI_EUNSUPPORTED;

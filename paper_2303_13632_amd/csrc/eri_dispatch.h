@@ -19,3 +19,9 @@ struct eri_kernel_info {
 // without a kernel have fn == nullptr.
 #define ERI_NCLASS5 625
 const eri_kernel_info* eri_kernel_table(int precision);
+
+// Launch variants of every class for the autotuner: entry id5 * ERI_MAXVAR + k,
+// k = 0 the default launch of the table above; unused entries have fn == nullptr.
+// All variants of a class share its orientation (perm) and output layout.
+#define ERI_MAXVAR 6
+const eri_kernel_info* eri_kernel_variants(int precision);

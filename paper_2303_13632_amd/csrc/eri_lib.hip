@@ -8,8 +8,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <numeric>
 #include <thread>
 #include <vector>
@@ -516,6 +519,8 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     return ERI_OK;
 }
 
+static const eri_kernel_info& class_kernel(const eri_plan* p, int c);
+
 extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
 {
     if (!p || !info) return ERI_EINVAL;
@@ -533,6 +538,15 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
         info->class_quartets[c] = p->class_count[c];
         info->class_ring[c] = p->class_ring[c];
         info->class_flops[c] = p->class_flops[c];
+        const eri_kernel_info& ki = class_kernel(p, c);
+        info->class_variant[c] = p->class_var[c];
+        info->class_mode[c] = ki.mode;
+        info->class_block[c] = ki.block;
+        info->class_per_block[c] = ki.per_block;
+        const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
+        int nv = 0;
+        while (nv < ERI_MAXVAR && var[class_id5_of(c) * ERI_MAXVAR + nv].fn) ++nv;
+        info->class_n_variants[c] = nv;
     }
     for (int c = 0; c <= 256; ++c) {
         info->class_eri_off[c] = p->class_eoff[c];
@@ -604,11 +618,22 @@ static int launch_items(const eri_kernel_info& ki, eri_class_args& a, hipStream_
     return ERI_OK;
 }
 
+// Kernel of a class launch: the autotuner's variant, else the default.
+static const eri_kernel_info& class_kernel(const eri_plan* p, int c)
+{
+    const int c5 = class_id5_of(c);
+    if (p->class_var[c] > 0) {
+        const eri_kernel_info& v = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0)[c5 * ERI_MAXVAR + p->class_var[c]];
+        if (v.fn) return v;
+    }
+    return kernel_table(p->precision)[c5];
+}
+
 static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
 {
     const int64_t n = p->class_count[c];
     if (n == 0) return ERI_OK;
-    const eri_kernel_info& ki = kernel_table(p->precision)[class_id5_of(c)];
+    const eri_kernel_info& ki = class_kernel(p, c);
     eri_class_args a;
     fill_args(p, c, a, out_eri, out_codes, out_scales);
     if (!p->batched) {
@@ -712,6 +737,193 @@ extern "C" int eri_compute_class(eri_plan* p, int32_t c, void* stream, double* o
     rc = launch_class(p, c, (hipStream_t)stream, out_eri, out_codes, out_scales);
     if (cur != p->device) (void)hipSetDevice(cur);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: timed trials of each class's launch variants on a sample
+// ---------------------------------------------------------------------------
+static std::string tune_key(const eri_plan* p, int c)
+{
+    char buf[64];
+    std::snprintf(buf, sizeof(buf), "%s:%d:%d", p->precision == ERI_FP32_MIXED ? "mixed" : "fp64", c, p->bits);
+    return buf;
+}
+
+// Cache file: one JSON object of "key": variant entries.
+static void read_tune_cache(const char* path, std::map<std::string, int>& out)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    size_t pos = 0;
+    while ((pos = text.find('"', pos)) != std::string::npos) {
+        const size_t end = text.find('"', pos + 1);
+        if (end == std::string::npos) break;
+        const std::string key = text.substr(pos + 1, end - pos - 1);
+        const size_t colon = text.find(':', end);
+        if (colon == std::string::npos) break;
+        char* stop = nullptr;
+        const long v = std::strtol(text.c_str() + colon + 1, &stop, 10);
+        if (stop != text.c_str() + colon + 1 && v >= 0 && v < ERI_MAXVAR) out[key] = (int)v;
+        pos = stop && stop > text.c_str() + end ? (size_t)(stop - text.c_str()) : end + 1;
+    }
+}
+
+static bool write_tune_cache(const char* path, const std::map<std::string, int>& m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto& e : m) std::fprintf(f, "  \"%s\": %d%s\n", e.first.c_str(), e.second, ++k < m.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, const char* cache_path)
+{
+    const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
+    std::map<std::string, int> cache;
+    if (cache_path) read_tune_cache(cache_path, cache);
+    // sample sizes and scratch outputs
+    std::vector<int64_t> nsample(256, 0);
+    int64_t max_vals = 1, max_q = 1;
+    for (int c = 0; c < 256; ++c) {
+        int64_t n = std::min(p->class_count[c], sample);
+        if (p->batched)
+            for (auto& b : p->bclass)
+                if (b.cid == c) n = std::min(n, b.chunk);
+        nsample[c] = n;
+        max_vals = std::max(max_vals, n * (int64_t)kernel_table(p->precision)[class_id5_of(c)].n_eriq);
+        max_q = std::max(max_q, n);
+    }
+    double* o_eri = nullptr;
+    void* o_codes = nullptr;
+    double* o_scales = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = ERI_OK;
+    auto hip = [&](hipError_t e) {
+        if (e != hipSuccess && rc == ERI_OK) {
+            g_last_hip = (int)e;
+            rc = e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP;
+        }
+    };
+    if (p->code_bytes) {
+        hip(hipMalloc(&o_codes, (size_t)max_vals * p->code_bytes));
+        hip(hipMalloc((void**)&o_scales, (size_t)max_q * sizeof(double)));
+    } else {
+        hip(hipMalloc((void**)&o_eri, (size_t)max_vals * sizeof(double)));
+    }
+    hip(hipEventCreate(&e0));
+    hip(hipEventCreate(&e1));
+    for (int c = 0; c < 256 && rc == ERI_OK; ++c) {
+        const int64_t n = nsample[c];
+        if (n == 0) continue;
+        const int c5 = class_id5_of(c);
+        int nv = 0;
+        for (int k = 0; k < ERI_MAXVAR; ++k) nv += var[c5 * ERI_MAXVAR + k].fn ? 1 : 0;
+        p->class_var[c] = 0;
+        if (nv <= 1) continue;
+        const std::string key = tune_key(p, c);
+        auto hit = cache.find(key);
+        if (hit != cache.end() && var[c5 * ERI_MAXVAR + hit->second].fn) {
+            p->class_var[c] = hit->second;
+            continue;
+        }
+        eri_class_args a;
+        std::memset(&a, 0, sizeof(a));
+        a.pairs = p->d_pairs;
+        a.prims = p->d_prims;
+        a.out_eri = o_eri;
+        a.out_codes = o_codes;
+        a.out_scales = o_scales;
+        a.cn = p->cn;
+        a.qmax = p->qmax;
+        a.code_bytes = p->code_bytes;
+        a.ring = n;
+        a.qbase = 0;
+        a.n_items = n;
+        if (!p->batched) {
+            a.items = p->d_items + p->class_qoff[c];
+        } else {
+            const eri_batch_class* bc = nullptr;
+            for (auto& b : p->bclass)
+                if (b.cid == c) bc = &b;
+            const auto sbeg = p->h_seg_off.begin();
+            const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, n) - sbeg);
+            hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - bc->seg_lo)), dim3(256), 0, st, p->d_seg_off,
+                               p->d_seg_p1, bc->seg_lo, bc->ket_lo, (int64_t)0, n, bc->swap ? 1 : 0, p->d_items);
+            hip(hipGetLastError());
+            a.items = p->d_items;
+        }
+        double best = 0.0;
+        int bestk = 0;
+        for (int k = 0; k < ERI_MAXVAR && rc == ERI_OK; ++k) {
+            const eri_kernel_info& ki = var[c5 * ERI_MAXVAR + k];
+            if (!ki.fn) continue;
+            rc = launch_items(ki, a, st);   // warm-up
+            hip(hipEventRecord(e0, st));
+            for (int t = 0; t < trials && rc == ERI_OK; ++t) rc = launch_items(ki, a, st);
+            hip(hipEventRecord(e1, st));
+            hip(hipEventSynchronize(e1));
+            float ms = 0.f;
+            hip(hipEventElapsedTime(&ms, e0, e1));
+            if (rc != ERI_OK) break;
+            if (k == 0 || ms < best) {
+                best = ms;
+                bestk = k;
+            }
+        }
+        p->class_var[c] = bestk;
+        cache[key] = bestk;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (o_eri) (void)hipFree(o_eri);
+    if (o_codes) (void)hipFree(o_codes);
+    if (o_scales) (void)hipFree(o_scales);
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    if (rc == ERI_OK && cache_path && !write_tune_cache(cache_path, cache)) rc = ERI_EINVAL;
+    return rc;
+}
+
+extern "C" int eri_plan_tune(eri_plan* p, void* stream, int64_t sample_quartets, int32_t trials, const char* cache_path)
+{
+    if (!p || sample_quartets < 1 || trials < 1) return ERI_EINVAL;
+    int cur = 0;
+    ERI_HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
+    int rc;
+    try {
+        rc = tune_plan(p, (hipStream_t)stream, sample_quartets, trials, cache_path);
+    } catch (const std::bad_alloc&) {
+        rc = ERI_ENOMEM;
+    }
+    if (cur != p->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
+extern "C" int eri_plan_set_variants(eri_plan* p, const int32_t* v)
+{
+    if (!p || !v) return ERI_EINVAL;
+    const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
+    for (int c = 0; c < 256; ++c)
+        if (v[c] < 0 || v[c] >= ERI_MAXVAR || !var[class_id5_of(c) * ERI_MAXVAR + v[c]].fn) return ERI_EINVAL;
+    for (int c = 0; c < 256; ++c) p->class_var[c] = v[c];
+    if (p->graph) {
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph = nullptr;
+    }
+    return ERI_OK;
 }
 
 // ---------------------------------------------------------------------------

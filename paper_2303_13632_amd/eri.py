@@ -54,7 +54,10 @@ class PlanInfo(ctypes.Structure):
                 ("batched", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("class_quartets", ctypes.c_int64 * 256), ("class_ring", ctypes.c_int64 * 256),
                 ("class_eri_off", ctypes.c_int64 * 257),
-                ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256)]
+                ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256),
+                ("class_variant", ctypes.c_int32 * 256), ("class_mode", ctypes.c_int32 * 256),
+                ("class_block", ctypes.c_int32 * 256), ("class_per_block", ctypes.c_int32 * 256),
+                ("class_n_variants", ctypes.c_int32 * 256)]
 
 
 _vp = ctypes.c_void_p
@@ -81,6 +84,8 @@ def load():
     lib.eri_compress.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
     lib.eri_decompress.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eri_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
+    lib.eri_plan_tune.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_char_p]
+    lib.eri_plan_set_variants.argtypes = [_vp, _i32p]
     lib.eri_plan_destroy.argtypes = [_vp]
     lib.eri_plan_destroy.restype = None
     lib.eri_status_string.argtypes = [ctypes.c_int]
@@ -172,8 +177,41 @@ class Plan:
         self.class_eri_off = np.array(info.class_eri_off[:], dtype=np.int64)
         self.class_quartet_off = np.array(info.class_quartet_off[:], dtype=np.int64)
         self.class_flops = np.array(info.class_flops[:], dtype=np.float64)
+        self._read_variants(info)
         self._pos = None
         self._eri_off = None
+
+    def _read_variants(self, info=None):
+        if info is None:
+            info = PlanInfo()
+            _check(load().eri_plan_info_get(self._h, ctypes.byref(info)), "eri_plan_info_get")
+        self.class_variant = np.array(info.class_variant[:], dtype=np.int32)
+        self.class_mode = np.array(info.class_mode[:], dtype=np.int32)
+        self.class_block = np.array(info.class_block[:], dtype=np.int32)
+        self.class_per_block = np.array(info.class_per_block[:], dtype=np.int32)
+        self.class_n_variants = np.array(info.class_n_variants[:], dtype=np.int32)
+
+    def tune(self, sample_quartets=65536, trials=3, cache=None, stream=None):
+        """eri_plan_tune: time each class's launch variants on a sample and keep
+        the fastest (choices cached in the JSON file `cache` when given)."""
+        path = None if cache is None else os.fsencode(cache)
+        _check(load().eri_plan_tune(self._h, _stream(stream), int(sample_quartets), int(trials), path),
+               "eri_plan_tune")
+        self._read_variants()
+        return self.class_variant.copy()
+
+    def set_variants(self, variants):
+        v = np.ascontiguousarray(variants, dtype=np.int32)
+        if v.shape != (256,):
+            raise ValueError("256 variants expected")
+        _check(load().eri_plan_set_variants(self._h, v), "eri_plan_set_variants")
+        self._read_variants()
+
+    def kernel_name(self, cid):
+        """Name of the kernel a class launch uses (variant included)."""
+        L = [(cid >> 6) & 3, (cid >> 4) & 3, (cid >> 2) & 3, cid & 3]
+        prec = "mixed" if self.precision == "mixed" else "fp64"
+        return "eri_%s_c%03d%s" % (prec, cid, "_a" if self.class_mode[cid] != _default_mode(L) else "")
 
     def layout(self):
         """(pos, eri_off) per user quartet (plan position, first ERI)."""
@@ -231,16 +269,17 @@ class Plan:
         """Cartesian basis functions of the shell set."""
         return int(sum(_ncart(l) for l in self.shells["L"]))
 
-    def backward(self, dl=None, density=None, grad_centers=None, grad_exps=None, energy=None, stream=None):
+    def backward(self, dl=None, density=None, grad_centers=None, grad_exps=None, energy=None, stream=None,
+                 energy_only=False):
         """eri_backward: adds dL/dxyz and dL/dexps of L = sum w Gbar (ab|cd)
         (Gbar = dl in the plan layout, or D D from a density) into the given
         device tensors, allocating zeroed ones when None.  Returns
         (grad_centers [n_shells, 3], grad_exps [n_prims], energy [1])."""
         import torch
         dev = torch.device("cuda", self.device)
-        if grad_centers is None:
+        if grad_centers is None and not energy_only:
             grad_centers = torch.zeros((len(self.shells["L"]), 3), dtype=torch.float64, device=dev)
-        if grad_exps is None:
+        if grad_exps is None and not energy_only:
             grad_exps = torch.zeros(max(self.n_prims, 1), dtype=torch.float64, device=dev)
         if energy is None:
             energy = torch.zeros(1, dtype=torch.float64, device=dev)
@@ -252,7 +291,7 @@ class Plan:
         nbf = 0 if density is None else int(density.shape[0])
         _check(load().eri_backward(self._h, _stream(stream), _ptr(dl), _ptr(density), nbf, _ptr(grad_centers),
                                    _ptr(grad_exps), _ptr(energy)), "eri_backward")
-        return grad_centers, grad_exps[: self.n_prims], energy
+        return grad_centers, None if grad_exps is None else grad_exps[: self.n_prims], energy
 
     def check_parameters(self, centers, exps):
         """The plan's integrals are those of its shell set: autograd inputs
@@ -286,6 +325,25 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _default_mode(L):
+    """Work mapping of a class's default kernel (0 lane per quartet, 1 slots),
+    as the generator chooses it."""
+    import importlib.util
+    global _codegen
+    if _codegen is None:
+        spec = importlib.util.spec_from_file_location("_eri_codegen", os.path.join(_PKG, "csrc", "codegen.py"))
+        _codegen = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(_codegen)
+    key = tuple(L)
+    if key not in _mode_cache:
+        _mode_cache[key] = 0 if _codegen.ClassPlan(*key).mode == "T" else 1
+    return _mode_cache[key]
+
+
+_codegen = None
+_mode_cache = {}
 
 
 def _ncart(L):

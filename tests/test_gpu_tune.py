@@ -1,0 +1,98 @@
+"""GPU tests of the launch variants and the autotuner: every variant of every
+class meets the parity bar against the oracle (so the tuner's choice cannot
+change what is computed), codes stay consistent with the values, and tuning
+choices round-trip through the JSON cache."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2303_13632_amd import workloads as W
+from parity_util import check_quartets
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+N_PER_CLASS = 67
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def all_classes():
+    from paper_2303_13632_amd import eri
+    parts = [W.class_case(cid, n_quartets=N_PER_CLASS, seed=W.SEED_BASE + 61) for cid in range(256)]
+    shells, quartets = W.merge(parts)
+    ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
+    plan = eri.Plan(shells, quartets, bits=16)
+    return shells, quartets, ref, ref_off, sizes, plan
+
+
+def _run(plan):
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    return (plan.to_user(e.cpu().numpy()[: plan.n_eri]), c.cpu().numpy()[: plan.n_eri].astype(np.int32),
+            s.cpu().numpy()[: plan.n_quartets], e.cpu().numpy()[: plan.n_eri])
+
+
+def test_every_variant_parity(all_classes):
+    shells, quartets, ref, ref_off, sizes, plan = all_classes
+    nv = plan.class_n_variants
+    assert nv.min() >= 1 and nv.max() <= 6
+    assert (nv > 1).sum() >= 100, "expected alternates for many classes"
+    for k in range(1, int(nv.max())):
+        v = np.where(nv > k, k, 0).astype(np.int32)
+        plan.set_variants(v)
+        print("variant %d: %d classes" % (k, int((v == k).sum())), flush=True)
+        got, codes, scales, plan_vals = _run(plan)
+        for c in np.nonzero(v == k)[0]:
+            qs = np.arange(c * N_PER_CLASS, (c + 1) * N_PER_CLASS)
+            lo, hi = ref_off[qs[0]], ref_off[qs[-1]] + sizes[qs[-1]]
+            check_quartets(shells, quartets[qs], got[lo:hi], ref[lo:hi], ref_off[qs] - lo, sizes[qs], THREADS)
+        # the fused codes are the compressor applied to the same doubles
+        off = []
+        for c in range(256):
+            n = int(plan.class_quartets[c])
+            if n:
+                m = int((plan.class_eri_off[c + 1] - plan.class_eri_off[c]) // n)
+                off.append(plan.class_eri_off[c] + m * np.arange(n))
+        off = np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
+        oc, oe = O.compress(16, plan_vals, off)
+        assert np.array_equal(oc, codes)
+        assert np.array_equal(oe, scales)
+    plan.set_variants(np.zeros(256, np.int32))
+
+
+def test_tune_and_cache(all_classes, tmp_path):
+    from paper_2303_13632_amd import eri
+    shells, quartets, ref, ref_off, sizes, plan = all_classes
+    cache = str(tmp_path / "tune.json")
+    choice = plan.tune(sample_quartets=N_PER_CLASS, trials=2, cache=cache)
+    assert np.all(choice < plan.class_n_variants)
+    data = json.load(open(cache))
+    assert len(data) == int((plan.class_n_variants > 1).sum())
+    assert all(k.startswith("fp64:") and k.endswith(":16") for k in data)
+    for k, v in data.items():
+        assert choice[int(k.split(":")[1])] == v
+    other = eri.Plan(shells, quartets, bits=16)
+    again = other.tune(sample_quartets=N_PER_CLASS, trials=2, cache=cache)
+    assert np.array_equal(again, choice)
+    got, _, _, _ = _run(other)
+    check_quartets(shells, quartets, got, ref, ref_off, sizes, THREADS)
+
+
+def test_tune_batched_plan():
+    """A screened plan keeps its results after tuning (the graph is
+    recaptured with the chosen kernels)."""
+    from paper_2303_13632_amd import eri
+    sh = W.molecule_basis(n_heavy=2, n_h=4, lattice=(2, 2, 2), seed=W.SEED_BASE + 62)
+    plan = eri.Plan(sh, None, bits=16, schwarz=1e-10)
+    e0, _, _ = plan.alloc(eri=True, codes=False)
+    plan.compute(e0)
+    plan.tune(sample_quartets=4096, trials=1)
+    e1, _, _ = plan.alloc(eri=True, codes=False)
+    plan.compute(e1)
+    torch.cuda.synchronize()
+    a, b = e0.cpu().numpy()[: plan.out_values], e1.cpu().numpy()[: plan.out_values]
+    assert np.all(np.abs(a - b) <= 1e-12 + 1e-14 * np.abs(a))
