@@ -78,6 +78,9 @@ def main():
                          "gradient: E = sum D D (ab|cd) and its gradient on the 64-atom basis")
     ap.add_argument("--molecule-scale", type=float, default=1.0, help="fraction of the molecule's atoms")
     ap.add_argument("--schwarz", type=float, default=1e-10)
+    ap.add_argument("--fd-sample", type=int, default=0,
+                    help="gradient workload: check this many coordinates and as many exponents by central "
+                         "differences (h = 1e-4) of the GPU energy")
     ap.add_argument("--ring-gb", type=float, default=48.0)
     args = ap.parse_args()
 
@@ -279,7 +282,40 @@ def bench_gradient(args):
         "energy": float(en.item()), "grad_centres_norm": float(gc.norm().item()),
         "grad_exps_norm": float(ge.norm().item()),
     }
+    if args.fd_sample > 0:
+        out["fd_check"] = fd_check(sh, D, gc.cpu().numpy(), ge.cpu().numpy(), args)
     print(json.dumps(out), flush=True)
+
+
+def fd_check(sh, D, gc, ge, args, h=1e-4):
+    """Central differences of the GPU energy (new screened plan per point,
+    energy-only eri_backward) for a seeded sample of coordinates and
+    exponents; errors relative to max(|g_FD|, 1e-8 max|g|)."""
+    import torch
+    from paper_2303_13632_amd import eri
+    rng = np.random.default_rng(20230323 + 5)
+    gmax = max(np.abs(gc).max(), np.abs(ge).max())
+
+    def energy(s2):
+        p2 = eri.Plan(s2, None, precision="fp64", bits=0, schwarz=args.schwarz)
+        _, _, en = p2.backward(density=D, energy_only=True)
+        return float(en.item())
+
+    rows = []
+    for key, n_all, g in (("xyz", 3 * len(sh["L"]), gc.reshape(-1)), ("exps", len(sh["exps"]), ge)):
+        for idx in rng.choice(n_all, size=min(args.fd_sample, n_all), replace=False):
+            vals = []
+            for d in (h, -h):
+                s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
+                s2[key].reshape(-1)[idx] += d
+                vals.append(energy(s2))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            rel = abs(fd - g[idx]) / max(abs(fd), 1e-8 * gmax)
+            rows.append({"param": key, "index": int(idx), "analytic": float(g[idx]), "fd": fd, "rel": rel})
+        log("fd %s done" % key)
+    return {"h": h, "n": len(rows), "max_rel": max(r["rel"] for r in rows),
+            "max_abs_over_gmax": max(abs(r["fd"] - r["analytic"]) for r in rows) / gmax,
+            "worst": max(rows, key=lambda r: r["rel"])}
 
 
 if __name__ == "__main__":

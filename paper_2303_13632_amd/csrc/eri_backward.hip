@@ -18,10 +18,15 @@
 // respect to D follows from translation invariance, dA + dB + dC + dD = 0.
 //
 // Pipeline per class and chunk of quartets: user items (P1, P2) -> for each
-// derivative kind a derived item list (derive kernel) -> the forward kernel of
-// the derived class writes FP64 blocks into scratch -> the contraction kernel
-// maps each derived block onto Gbar and adds the sums into the gradients with
-// FP64 atomics.
+// derivative kind a derived item list (derive kernel; for the exponent kinds
+// one item per primitive of the differentiated shell, compacted by a scan) ->
+// the forward kernel of the derived class writes FP64 blocks into scratch ->
+// the contraction kernel maps each derived block onto Gbar.  Contraction
+// blocks sum into an LDS copy of the gradient, which each block adds into its
+// own slice of a partial-sum buffer (no atomics on global memory); one final
+// kernel adds the slices into the caller's arrays.  Gradients too large for
+// LDS fall back to global FP64 atomics.  Either way the order of the atomic
+// additions, and so the last bits of the sums, may vary between calls.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,6 +34,8 @@
 #include <cstring>
 #include <new>
 #include <vector>
+
+#include <hipcub/hipcub.hpp>
 
 #include "eri_internal.h"
 
@@ -41,6 +48,8 @@ enum { DK_BASE = -1, DK_PLUS = 0, DK_MINUS = 1, DK_E0 = 2, DK_E2 = 3 };
 constexpr int BWD_MAXL = 2;                       // shells of the differentiated basis
 constexpr int64_t BWD_SCRATCH_MAX = (int64_t)1 << 28;   // doubles (2 GiB)
 constexpr int64_t BWD_CHUNK_MAX = (int64_t)1 << 22;     // quartets per pass
+constexpr int BWD_SLICES = 1024;                  // contraction blocks (partial-sum slices)
+constexpr int BWD_LDS_MAX = 4096;                 // gradient entries kept in LDS (32 KB)
 
 __host__ __device__ inline int kind_shift(int kind) { return kind == DK_PLUS ? 1 : kind == DK_MINUS ? -1 : kind == DK_E2 ? 2 : 0; }
 
@@ -62,14 +71,25 @@ struct eri_bwd_state {
     int64_t chunk_cap = 0;
     int64_t scratch_elems = 0;
     int kmax[BWD_MAXL + 1] = {};  // largest K among shells of each L
+    int kmax_all = 1;
+    int32_t* d_cnt = nullptr;     // per quartet of a pass: primitives of the differentiated shell
+    int32_t* d_off = nullptr;     // their exclusive prefix sums
+    int32_t* d_origin = nullptr;  // exponent items: quartet | (primitive << 24)
+    void* d_scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+    int64_t n_grad = 0;           // 3 n_shells + n_prims + 1 (energy)
+    double* d_part = nullptr;     // BWD_SLICES partial gradients (LDS mode)
+    int32_t* h_pin = nullptr;     // pinned host word for scan totals
 };
 
 void eri_bwd_free(eri_bwd_state* b)
 {
     if (!b) return;
-    void* ptrs[] = {b->d_pairs, b->d_prims, b->d_dmap, b->d_uall, b->d_uitems, b->d_ditems, b->d_scratch, b->d_bf, b->d_poff};
+    void* ptrs[] = {b->d_pairs, b->d_prims, b->d_dmap,   b->d_uall,     b->d_uitems, b->d_ditems, b->d_scratch,
+                    b->d_bf,    b->d_poff,  b->d_cnt,    b->d_off,      b->d_origin, b->d_scan_tmp, b->d_part};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
+    if (b->h_pin) (void)hipHostFree(b->h_pin);
     delete b;
 }
 
@@ -100,13 +120,17 @@ __device__ __forceinline__ int comp_index(int lx, int ly, int lz)
 // eq1/eq2: derived pair 1/2 has equal angular momenta, so a reversed record
 // is flagged for the kernel).
 __global__ __launch_bounds__(256) void eri_bwd_derive_kernel(const eri_item* __restrict__ uitems, int64_t n,
+                                                             const int32_t* __restrict__ origin,
                                                              const eri_shell_pair* __restrict__ pairs,
                                                              const int32_t* __restrict__ dmap, int pair, int pos,
-                                                             int kind, int k, int32_t null_rec, int kswap, int eq1,
+                                                             int kind, int32_t null_rec, int kswap, int eq1,
                                                              int eq2, eri_item* __restrict__ out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    // item j is user quartet i; exponent kinds carry the primitive k
+    const int64_t i = origin ? (int64_t)(origin[j] & 0xffffff) : j;
+    const int k = origin ? (origin[j] >> 24) : 0;
     const eri_item u = uitems[i];
     int32_t rec[2] = {u.bra & 0x7fffffff, u.ket & 0x7fffffff};
     int rev[2] = {u.bra < 0 ? 1 : 0, u.ket < 0 ? 1 : 0};
@@ -129,51 +153,94 @@ __global__ __launch_bounds__(256) void eri_bwd_derive_kernel(const eri_item* __r
     eri_item o;
     o.bra = kswap ? b2 : b1;
     o.ket = kswap ? b1 : b2;
-    out[i] = o;
+    out[j] = o;
+}
+
+// Primitive count of the shell at user position `pos` of each quartet.
+__global__ __launch_bounds__(256) void eri_bwd_count_kernel(const eri_item* __restrict__ uitems, int64_t n,
+                                                            const eri_shell_pair* __restrict__ pairs, int pos,
+                                                            int32_t* __restrict__ cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const eri_item u = uitems[i];
+    const int32_t r = pos < 2 ? u.bra : u.ket;
+    const eri_shell_pair P = pairs[r & 0x7fffffff];
+    const int side = (pos & 1) ^ (r < 0 ? 1 : 0);
+    cnt[i] = side == 0 ? P.nprim / P.kb : P.kb;
+}
+
+// Exponent items: quartet i owns entries off[i] .. off[i] + cnt[i] - 1.
+__global__ __launch_bounds__(256) void eri_bwd_origin_kernel(const int32_t* __restrict__ cnt,
+                                                             const int32_t* __restrict__ off, int64_t n,
+                                                             int32_t* __restrict__ origin)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    for (int k = 0; k < cnt[i]; ++k) origin[off[i] + k] = (int32_t)i | (k << 24);
+}
+
+__global__ __launch_bounds__(256) void eri_bwd_zero_kernel(double* __restrict__ x, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) x[t] = 0.0;
+}
+
+// grad_c / grad_e / energy += sum over slices, in slice order.
+__global__ __launch_bounds__(256) void eri_bwd_reduce_kernel(const double* __restrict__ part, int64_t n_grad,
+                                                             int64_t ns3, double* __restrict__ grad_c,
+                                                             double* __restrict__ grad_e, double* __restrict__ energy)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= n_grad) return;
+    double v = 0.0;
+    for (int b = 0; b < BWD_SLICES; ++b) v += part[(int64_t)b * n_grad + t];
+    if (t < ns3) {
+        if (grad_c) grad_c[t] += v;
+    } else if (t < n_grad - 1) {
+        if (grad_e) grad_e[t - ns3] += v;
+    } else if (energy) {
+        energy[0] += v;
+    }
 }
 
 struct bwd_contract_args {
     const eri_item* uitems;
-    int64_t n;
+    int64_t n;                  // items (derived blocks)
+    const int32_t* origin;      // exponent kinds: item -> quartet | (primitive << 24); else null
     const eri_shell_pair* pairs;
-    const double* blk;          // derived blocks, one per user item
+    const double* blk;          // derived blocks, one per item
     const double* dl;           // dL/dERI in plan layout, or null
     int64_t dl_base;            // index in dl of the first ERI of the pass's first quartet
     const double* dens;         // density (nbf x nbf), or null
     int64_t nbf;
     const int64_t* bf;
     const int64_t* poff;
-    double* grad_c;
+    double* grad_c;             // global atomics mode
     double* grad_e;
     double* energy;
+    double* part;               // LDS mode: slices of n_grad partial sums, or null
+    int64_t n_grad;
+    int64_t ns3;                // 3 n_shells
     int32_t L[4];               // user angular momenta of the class
     int32_t pos;                // differentiated user position (kinds other than base)
     int32_t kind;
-    int32_t k;                  // primitive of the differentiated shell (exponent kinds)
+    int32_t group;              // lanes per item: 1, 2, ..., 64
     int32_t degen;              // weight quartets by their degeneracy in the full sum
 };
 
-// One wavefront per user quartet: sum over its ERIs of Gbar times the mapped
-// derived ERIs, then one atomic add per gradient entry.
-__global__ __launch_bounds__(64) void eri_bwd_contract_kernel(bwd_contract_args A)
+// Groups of `group` lanes per item: sum over the quartet's ERIs of Gbar times
+// the mapped derived ERIs, reduced across the group.
+__global__ __launch_bounds__(256) void eri_bwd_contract_kernel(bwd_contract_args A)
 {
-    const int64_t i = blockIdx.x;
-    const int lane = threadIdx.x;
-    const eri_item u = A.uitems[i];
-    const int32_t p1 = u.bra & 0x7fffffff, p2 = u.ket & 0x7fffffff;
-    const eri_shell_pair P1 = A.pairs[p1], P2 = A.pairs[p2];
-    int32_t sh[4];
-    sh[0] = u.bra < 0 ? P1.sb : P1.sa;
-    sh[1] = u.bra < 0 ? P1.sa : P1.sb;
-    sh[2] = u.ket < 0 ? P2.sb : P2.sa;
-    sh[3] = u.ket < 0 ? P2.sa : P2.sb;
-    if (A.kind >= DK_E0) {
-        // primitive k of the differentiated shell: none when k >= K
-        const eri_shell_pair& P = A.pos < 2 ? P1 : P2;
-        const int side = (A.pos & 1) ^ ((A.pos < 2 ? u.bra : u.ket) < 0 ? 1 : 0);
-        const int K = side == 0 ? P.nprim / P.kb : P.kb;
-        if (A.k >= K) return;
+    extern __shared__ double s_g[];
+    const bool lds = A.part != nullptr;
+    if (lds) {
+        for (int64_t t = threadIdx.x; t < A.n_grad; t += 256) s_g[t] = 0.0;
+        __syncthreads();
     }
+    const int G = A.group;
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t per_block = 256 / G;
     int nc[4], nd[4];
     for (int x = 0; x < 4; ++x) {
         nc[x] = (A.L[x] + 1) * (A.L[x] + 2) / 2;
@@ -185,72 +252,93 @@ __global__ __launch_bounds__(64) void eri_bwd_contract_kernel(bwd_contract_args 
     const int n_eriq = nc[0] * nc[1] * nc[2] * nc[3];
     const int st[4] = {nd[1] * nd[2] * nd[3], nd[2] * nd[3], nd[3], 1};
     const int64_t nblk = (int64_t)nd[0] * st[0];
-    const double* b = A.blk + i * nblk;
-    double w = 1.0;
-    if (A.degen) {
-        if (sh[0] != sh[1]) w *= 2.0;
-        if (sh[2] != sh[3]) w *= 2.0;
-        if (p1 != p2) w *= 2.0;
-    }
-    int64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-    if (!A.dl) {
-        f0 = A.bf[sh[0]]; f1 = A.bf[sh[1]]; f2 = A.bf[sh[2]]; f3 = A.bf[sh[3]];
-    }
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-    for (int o = lane; o < n_eriq; o += 64) {
-        int ci[4];
-        int rem = o;
-        ci[3] = rem % nc[3]; rem /= nc[3];
-        ci[2] = rem % nc[2]; rem /= nc[2];
-        ci[1] = rem % nc[1]; rem /= nc[1];
-        ci[0] = rem;
-        double g;
-        if (A.dl) {
-            g = A.dl[A.dl_base + i * n_eriq + o];
+    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / G; j < A.n; j += (int64_t)gridDim.x * per_block) {
+        const int64_t i = A.origin ? (int64_t)(A.origin[j] & 0xffffff) : j;
+        const int k = A.origin ? (A.origin[j] >> 24) : 0;
+        const eri_item u = A.uitems[i];
+        const int32_t p1 = u.bra & 0x7fffffff, p2 = u.ket & 0x7fffffff;
+        const eri_shell_pair P1 = A.pairs[p1], P2 = A.pairs[p2];
+        int32_t sh[4];
+        sh[0] = u.bra < 0 ? P1.sb : P1.sa;
+        sh[1] = u.bra < 0 ? P1.sa : P1.sb;
+        sh[2] = u.ket < 0 ? P2.sb : P2.sa;
+        sh[3] = u.ket < 0 ? P2.sa : P2.sb;
+        const double* b = A.blk + j * nblk;
+        double w = 1.0;
+        if (A.degen) {
+            if (sh[0] != sh[1]) w *= 2.0;
+            if (sh[2] != sh[3]) w *= 2.0;
+            if (p1 != p2) w *= 2.0;
+        }
+        int64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+        if (!A.dl) {
+            f0 = A.bf[sh[0]]; f1 = A.bf[sh[1]]; f2 = A.bf[sh[2]]; f3 = A.bf[sh[3]];
+        }
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+        for (int o = gl; o < n_eriq; o += G) {
+            int ci[4];
+            int rem = o;
+            ci[3] = rem % nc[3]; rem /= nc[3];
+            ci[2] = rem % nc[2]; rem /= nc[2];
+            ci[1] = rem % nc[1]; rem /= nc[1];
+            ci[0] = rem;
+            double g;
+            if (A.dl) {
+                g = A.dl[A.dl_base + i * n_eriq + o];
+            } else {
+                g = A.dens[(f0 + ci[0]) * A.nbf + f1 + ci[1]] * A.dens[(f2 + ci[2]) * A.nbf + f3 + ci[3]];
+            }
+            if (g == 0.0) continue;
+            if (A.kind == DK_BASE || A.kind == DK_E0) {
+                acc0 += g * b[o];
+                continue;
+            }
+            int base = 0;
+            for (int x = 0; x < 4; ++x)
+                if (x != dpos) base += ci[x] * st[x];
+            const int sd = st[dpos];
+            const int La = A.L[dpos];
+            const int lx = c_comp[La][ci[dpos]][0], ly = c_comp[La][ci[dpos]][1], lz = c_comp[La][ci[dpos]][2];
+            if (A.kind == DK_PLUS) {
+                acc0 += g * b[base + comp_index(lx + 1, ly, lz) * sd];
+                acc1 += g * b[base + comp_index(lx, ly + 1, lz) * sd];
+                acc2 += g * b[base + comp_index(lx, ly, lz + 1) * sd];
+            } else if (A.kind == DK_MINUS) {
+                if (lx) acc0 -= g * lx * b[base + comp_index(lx - 1, ly, lz) * sd];
+                if (ly) acc1 -= g * ly * b[base + comp_index(lx, ly - 1, lz) * sd];
+                if (lz) acc2 -= g * lz * b[base + comp_index(lx, ly, lz - 1) * sd];
+            } else {
+                acc0 += g * (b[base + comp_index(lx + 2, ly, lz) * sd] + b[base + comp_index(lx, ly + 2, lz) * sd] +
+                             b[base + comp_index(lx, ly, lz + 2) * sd]);
+            }
+        }
+        for (int s = G >> 1; s > 0; s >>= 1) {
+            acc0 += __shfl_xor(acc0, s);
+            acc1 += __shfl_xor(acc1, s);
+            acc2 += __shfl_xor(acc2, s);
+        }
+        if (gl != 0) continue;
+        acc0 *= w; acc1 *= w; acc2 *= w;
+        double* gc = lds ? s_g : A.grad_c;
+        double* ge = lds ? s_g + A.ns3 : A.grad_e;
+        double* en = lds ? s_g + A.n_grad - 1 : A.energy;
+        if (A.kind == DK_BASE) {
+            atomicAdd(en, acc0);
+        } else if (A.kind == DK_PLUS || A.kind == DK_MINUS) {
+            const double v[3] = {acc0, acc1, acc2};
+            for (int x = 0; x < 3; ++x) {
+                atomicAdd(gc + 3 * (int64_t)sh[dpos] + x, v[x]);
+                atomicAdd(gc + 3 * (int64_t)sh[3] + x, -v[x]);
+            }
         } else {
-            g = A.dens[(f0 + ci[0]) * A.nbf + f1 + ci[1]] * A.dens[(f2 + ci[2]) * A.nbf + f3 + ci[3]];
-        }
-        if (g == 0.0) continue;
-        if (A.kind == DK_BASE || A.kind == DK_E0) {
-            acc0 += g * b[o];
-            continue;
-        }
-        int base = 0;
-        for (int x = 0; x < 4; ++x)
-            if (x != dpos) base += ci[x] * st[x];
-        const int sd = st[dpos];
-        const int La = A.L[dpos];
-        const int lx = c_comp[La][ci[dpos]][0], ly = c_comp[La][ci[dpos]][1], lz = c_comp[La][ci[dpos]][2];
-        if (A.kind == DK_PLUS) {
-            acc0 += g * b[base + comp_index(lx + 1, ly, lz) * sd];
-            acc1 += g * b[base + comp_index(lx, ly + 1, lz) * sd];
-            acc2 += g * b[base + comp_index(lx, ly, lz + 1) * sd];
-        } else if (A.kind == DK_MINUS) {
-            if (lx) acc0 -= g * lx * b[base + comp_index(lx - 1, ly, lz) * sd];
-            if (ly) acc1 -= g * ly * b[base + comp_index(lx, ly - 1, lz) * sd];
-            if (lz) acc2 -= g * lz * b[base + comp_index(lx, ly, lz - 1) * sd];
-        } else {
-            acc0 += g * (b[base + comp_index(lx + 2, ly, lz) * sd] + b[base + comp_index(lx, ly + 2, lz) * sd] +
-                         b[base + comp_index(lx, ly, lz + 2) * sd]);
+            atomicAdd(ge + A.poff[sh[dpos]] + k, acc0);
         }
     }
-    for (int s = 32; s > 0; s >>= 1) {
-        acc0 += __shfl_xor(acc0, s);
-        acc1 += __shfl_xor(acc1, s);
-        acc2 += __shfl_xor(acc2, s);
-    }
-    if (lane != 0) return;
-    acc0 *= w; acc1 *= w; acc2 *= w;
-    if (A.kind == DK_BASE) {
-        atomicAdd(A.energy, acc0);
-    } else if (A.kind == DK_PLUS || A.kind == DK_MINUS) {
-        const double v[3] = {acc0, acc1, acc2};
-        for (int x = 0; x < 3; ++x) {
-            atomicAdd(A.grad_c + 3 * (int64_t)sh[dpos] + x, v[x]);
-            atomicAdd(A.grad_c + 3 * (int64_t)sh[3] + x, -v[x]);
-        }
-    } else {
-        atomicAdd(A.grad_e + A.poff[sh[dpos]] + A.k, acc0);
+    if (lds) {
+        __syncthreads();
+        double* mine = A.part + (int64_t)blockIdx.x * A.n_grad;
+        for (int64_t t = threadIdx.x; t < A.n_grad; t += 256)
+            if (s_g[t] != 0.0) mine[t] += s_g[t];
     }
 }
 
@@ -420,8 +508,14 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
         maxcount = std::max(maxcount, p->class_count[c]);
         maxnd = std::max(maxnd, nd);
     }
-    st->chunk_cap = std::max<int64_t>(1, std::min({maxcount, BWD_CHUNK_MAX, BWD_SCRATCH_MAX / maxnd}));
-    st->scratch_elems = st->chunk_cap * maxnd;
+    for (int l = 0; l <= BWD_MAXL; ++l) st->kmax_all = std::max(st->kmax_all, st->kmax[l]);
+    // passes of small classes take up to BWD_CHUNK_MAX quartets; larger derived
+    // blocks shorten the pass so that one kind's blocks fit the scratch
+    st->chunk_cap = std::max<int64_t>(1, std::min(maxcount, BWD_CHUNK_MAX));
+    st->scratch_elems = std::min(BWD_SCRATCH_MAX, st->chunk_cap * maxnd * st->kmax_all);
+    int64_t nprim_all = 0;
+    for (int64_t s = 0; s < ns; ++s) nprim_all = std::max<int64_t>(nprim_all, orig.off[s] + orig.K[s]);
+    st->n_grad = 3 * ns + nprim_all + 1;
     int rc = ERI_OK;
     auto up = [&](void** dst, const void* src, size_t bytes) {
         if (rc == ERI_OK) rc = upload(p, dst, src, bytes);
@@ -431,7 +525,27 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
     up((void**)&st->d_dmap, dmap.empty() ? nullptr : dmap.data(), dmap.size() * sizeof(int32_t));
     if (!p->batched) up((void**)&st->d_uall, uall.empty() ? nullptr : uall.data(), uall.size() * sizeof(eri_item));
     else up((void**)&st->d_uitems, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
-    up((void**)&st->d_ditems, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
+    up((void**)&st->d_ditems, nullptr, (size_t)(st->chunk_cap * st->kmax_all) * sizeof(eri_item));
+    up((void**)&st->d_cnt, nullptr, (size_t)st->chunk_cap * sizeof(int32_t));
+    up((void**)&st->d_off, nullptr, (size_t)st->chunk_cap * sizeof(int32_t));
+    up((void**)&st->d_origin, nullptr, (size_t)(st->chunk_cap * st->kmax_all) * sizeof(int32_t));
+    if (rc == ERI_OK) {
+        hipError_t e = hipcub::DeviceScan::ExclusiveSum(nullptr, st->scan_tmp_bytes, st->d_cnt, st->d_off,
+                                                        (int)st->chunk_cap, (hipStream_t)0);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            rc = ERI_EHIP;
+        }
+    }
+    up((void**)&st->d_scan_tmp, nullptr, std::max<size_t>(st->scan_tmp_bytes, 64));
+    if (st->n_grad <= BWD_LDS_MAX) up((void**)&st->d_part, nullptr, (size_t)BWD_SLICES * st->n_grad * sizeof(double));
+    if (rc == ERI_OK) {
+        hipError_t e = hipHostMalloc((void**)&st->h_pin, 2 * sizeof(int32_t), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            rc = ERI_ENOMEM;
+        }
+    }
     up((void**)&st->d_scratch, nullptr, (size_t)st->scratch_elems * sizeof(double));
     up((void**)&st->d_bf, bf.data(), bf.size() * sizeof(int64_t));
     up((void**)&st->d_poff, p->sh_off.empty() ? nullptr : p->sh_off.data(), p->sh_off.size() * sizeof(int64_t));
@@ -443,43 +557,105 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
     return ERI_OK;
 }
 
-struct bwd_kind {
-    int pos;    // user position 0..3 (0 for the base kind)
-    int kind;
-    int k;
+// Derived class of a kind and its n_ERIQ.
+static void derived_ls(const int L[4], int pos, int kind, int Lp[4])
+{
+    for (int x = 0; x < 4; ++x) Lp[x] = L[x];
+    if (kind != DK_BASE) Lp[pos] += kind_shift(kind);
+}
+
+struct bwd_call {
+    const double* dl;
+    const double* dens;
+    double* grad_c;
+    double* grad_e;
+    double* energy;
+    bool lds;
 };
 
-int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const double* dl, const double* dens,
-              double* grad_c, double* grad_e, double* energy)
+// One derived kind over `m` items: derive, forward kernel of the derived
+// class into scratch, contraction.
+static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const eri_item* uitems, int64_t m,
+                    const int32_t* origin, int pos, int kind, int64_t q0, const bwd_call& call)
+{
+    if (m == 0) return ERI_OK;
+    const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
+    int Lp[4];
+    derived_ls(L, pos, kind, Lp);
+    const eri_kernel_info& ki = kernel_table(ERI_FP64)[class_id5(Lp[0], Lp[1], Lp[2], Lp[3])];
+    if (!ki.fn) return ERI_EUNSUPPORTED;
+    const int kswap = (ki.perm & 3) >= 2 ? 1 : 0;
+    const unsigned g256 = (unsigned)((m + 255) / 256);
+    hipLaunchKernelGGL(eri_bwd_derive_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, origin, st->d_pairs,
+                       st->d_dmap, pos / 2, pos % 2, kind, st->null_rec, kswap, Lp[0] == Lp[1] ? 1 : 0,
+                       Lp[2] == Lp[3] ? 1 : 0, st->d_ditems);
+    ERI_HIP_TRY(hipGetLastError());
+    eri_class_args a;
+    std::memset(&a, 0, sizeof(a));
+    a.items = st->d_ditems;
+    a.n_items = m;
+    a.pairs = st->d_pairs;
+    a.prims = st->d_prims;
+    a.out_eri = st->d_scratch;
+    a.ring = m;
+    a.qbase = 0;
+    const int64_t grid = (m + ki.per_block - 1) / ki.per_block;
+    if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
+    void* args[] = {&a};
+    ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, strm));
+    bwd_contract_args ca;
+    std::memset(&ca, 0, sizeof(ca));
+    ca.uitems = uitems;
+    ca.n = m;
+    ca.origin = origin;
+    ca.pairs = st->d_pairs;
+    ca.blk = st->d_scratch;
+    ca.dl = call.dl;
+    const int n_eriq = ncart(L[0]) * ncart(L[1]) * ncart(L[2]) * ncart(L[3]);
+    ca.dl_base = p->class_eoff[c] + q0 * (int64_t)n_eriq;
+    ca.dens = call.dens;
+    ca.nbf = st->nbf;
+    ca.bf = st->d_bf;
+    ca.poff = st->d_poff;
+    ca.grad_c = call.grad_c;
+    ca.grad_e = call.grad_e;
+    ca.energy = call.energy;
+    ca.part = call.lds ? st->d_part : nullptr;
+    ca.n_grad = st->n_grad;
+    ca.ns3 = 3 * (int64_t)p->sh_L.size();
+    for (int x = 0; x < 4; ++x) ca.L[x] = L[x];
+    ca.pos = pos;
+    ca.kind = kind;
+    int G = 1;
+    while (G < 64 && G < n_eriq) G <<= 1;
+    ca.group = G;
+    ca.degen = p->batched ? 1 : 0;
+    const int64_t per_block = 256 / G;
+    const int64_t blocks = std::min<int64_t>(BWD_SLICES, (m + per_block - 1) / per_block);
+    const size_t lds = call.lds ? (size_t)st->n_grad * sizeof(double) : 0;
+    hipLaunchKernelGGL(eri_bwd_contract_kernel, dim3((unsigned)blocks), dim3(256), lds, strm, ca);
+    ERI_HIP_TRY(hipGetLastError());
+    return ERI_OK;
+}
+
+int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd_call& call)
 {
     const int64_t n = p->class_count[c];
     const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
-    const eri_kernel_info* tab = kernel_table(ERI_FP64);
-    std::vector<bwd_kind> kinds;
-    if (energy) kinds.push_back({0, DK_BASE, 0});
-    for (int x = 0; x < 3 && grad_c; ++x) {
-        kinds.push_back({x, DK_PLUS, 0});
-        if (L[x] >= 1) kinds.push_back({x, DK_MINUS, 0});
-    }
-    for (int x = 0; x < 4 && grad_c; ++x)
-        for (int k = 0; k < st->kmax[L[x]]; ++k) {
-            kinds.push_back({x, DK_E0, k});
-            kinds.push_back({x, DK_E2, k});
-        }
+    // largest derived block of the class, and quartets per pass
     int64_t maxnd = 1;
-    for (const auto& kd : kinds) {
+    for (int x = 0; x < 4; ++x) {
         int64_t nd = 1;
-        for (int x = 0; x < 4; ++x) nd *= ncart(L[x] + (kd.kind != DK_BASE && x == kd.pos ? kind_shift(kd.kind) : 0));
+        for (int y = 0; y < 4; ++y) nd *= ncart(L[y] + (y == x ? 2 : 0));
         maxnd = std::max(maxnd, nd);
     }
-    const int64_t chunk = std::max<int64_t>(1, std::min(st->chunk_cap, st->scratch_elems / maxnd));
+    const int64_t chunk = std::max<int64_t>(1, std::min(st->chunk_cap, st->scratch_elems / (maxnd * st->kmax_all)));
     const eri_batch_class* bc = nullptr;
     if (p->batched) {
         for (auto& b : p->bclass)
             if (b.cid == c) bc = &b;
         if (!bc) return ERI_OK;
     }
-    const int n_eriq = ncart(L[0]) * ncart(L[1]) * ncart(L[2]) * ncart(L[3]);
     for (int64_t q0 = 0; q0 < n; q0 += chunk) {
         const int64_t q1 = std::min(n, q0 + chunk), m = q1 - q0;
         const eri_item* uitems;
@@ -495,52 +671,31 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const dou
         } else {
             uitems = st->d_uall + p->class_qoff[c] + q0;
         }
-        for (const auto& kd : kinds) {
-            int Lp[4] = {L[0], L[1], L[2], L[3]};
-            if (kd.kind != DK_BASE) Lp[kd.pos] += kind_shift(kd.kind);
-            const eri_kernel_info& ki = tab[class_id5(Lp[0], Lp[1], Lp[2], Lp[3])];
-            if (!ki.fn) return ERI_EUNSUPPORTED;
-            const int kswap = (ki.perm & 3) >= 2 ? 1 : 0;
-            const unsigned g256 = (unsigned)((m + 255) / 256);
-            hipLaunchKernelGGL(eri_bwd_derive_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, st->d_pairs, st->d_dmap,
-                               kd.pos / 2, kd.pos % 2, kd.kind, kd.k, st->null_rec, kswap, Lp[0] == Lp[1] ? 1 : 0,
-                               Lp[2] == Lp[3] ? 1 : 0, st->d_ditems);
+        if (call.energy) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, 0, DK_BASE, q0, call));
+        if (!call.grad_c) continue;
+        for (int x = 0; x < 3; ++x) {
+            ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, x, DK_PLUS, q0, call));
+            if (L[x] >= 1) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, x, DK_MINUS, q0, call));
+        }
+        // exponent kinds: one item per primitive of the shell at position x
+        const unsigned g256 = (unsigned)((m + 255) / 256);
+        for (int x = 0; x < 4; ++x) {
+            hipLaunchKernelGGL(eri_bwd_count_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, st->d_pairs, x,
+                               st->d_cnt);
             ERI_HIP_TRY(hipGetLastError());
-            eri_class_args a;
-            std::memset(&a, 0, sizeof(a));
-            a.items = st->d_ditems;
-            a.n_items = m;
-            a.pairs = st->d_pairs;
-            a.prims = st->d_prims;
-            a.out_eri = st->d_scratch;
-            a.ring = m;
-            a.qbase = 0;
-            const int64_t grid = (m + ki.per_block - 1) / ki.per_block;
-            if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
-            void* args[] = {&a};
-            ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, strm));
-            bwd_contract_args ca;
-            std::memset(&ca, 0, sizeof(ca));
-            ca.uitems = uitems;
-            ca.n = m;
-            ca.pairs = st->d_pairs;
-            ca.blk = st->d_scratch;
-            ca.dl = dl;
-            ca.dl_base = p->class_eoff[c] + q0 * (int64_t)n_eriq;
-            ca.dens = dens;
-            ca.nbf = st->nbf;
-            ca.bf = st->d_bf;
-            ca.poff = st->d_poff;
-            ca.grad_c = grad_c;
-            ca.grad_e = grad_e;
-            ca.energy = energy;
-            for (int x = 0; x < 4; ++x) ca.L[x] = L[x];
-            ca.pos = kd.pos;
-            ca.kind = kd.kind;
-            ca.k = kd.k;
-            ca.degen = p->batched ? 1 : 0;
-            hipLaunchKernelGGL(eri_bwd_contract_kernel, dim3((unsigned)m), dim3(64), 0, strm, ca);
+            size_t tmp = st->scan_tmp_bytes;
+            ERI_HIP_TRY(hipcub::DeviceScan::ExclusiveSum(st->d_scan_tmp, tmp, st->d_cnt, st->d_off, (int)m, strm));
+            hipLaunchKernelGGL(eri_bwd_origin_kernel, dim3(g256), dim3(256), 0, strm, st->d_cnt, st->d_off, m,
+                               st->d_origin);
             ERI_HIP_TRY(hipGetLastError());
+            ERI_HIP_TRY(hipMemcpyAsync(st->h_pin, st->d_off + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, strm));
+            ERI_HIP_TRY(hipMemcpyAsync(st->h_pin + 1, st->d_cnt + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost,
+                                       strm));
+            ERI_HIP_TRY(hipStreamSynchronize(strm));
+            const int64_t total = (int64_t)st->h_pin[0] + st->h_pin[1];
+            if (total > m * st->kmax_all) return ERI_EHIP;   // cannot happen: K <= kmax
+            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, x, DK_E0, q0, call));
+            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, x, DK_E2, q0, call));
         }
     }
     return ERI_OK;
@@ -571,9 +726,21 @@ extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, co
         }
     }
     if (rc == ERI_OK && density && nbf != p->bwd->nbf) rc = ERI_EINVAL;
+    eri_bwd_state* st = p->bwd;
+    hipStream_t strm = (hipStream_t)stream;
+    const bwd_call call{dl_deri, density, grad_centers, grad_exps, energy, st && st->d_part != nullptr};
+    if (rc == ERI_OK && call.lds) {
+        hipLaunchKernelGGL(eri_bwd_zero_kernel, dim3(1024), dim3(256), 0, strm, st->d_part,
+                           (int64_t)BWD_SLICES * st->n_grad);
+        if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
+    }
     for (int c = 0; c < 256 && rc == ERI_OK; ++c)
-        if (p->class_count[c])
-            rc = run_class(p, p->bwd, c, (hipStream_t)stream, dl_deri, density, grad_centers, grad_exps, energy);
+        if (p->class_count[c]) rc = run_class(p, st, c, strm, call);
+    if (rc == ERI_OK && call.lds) {
+        hipLaunchKernelGGL(eri_bwd_reduce_kernel, dim3((unsigned)((st->n_grad + 255) / 256)), dim3(256), 0, strm,
+                           st->d_part, st->n_grad, 3 * (int64_t)p->sh_L.size(), grad_centers, grad_exps, energy);
+        if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
+    }
     if (cur != p->device) (void)hipSetDevice(cur);
     return rc;
 }

@@ -180,3 +180,37 @@ def test_errors_and_empty():
     assert ex.value.status == eri.ERI_ESTATE
     with pytest.raises(eri.EriError):
         ring.backward(density=torch.zeros((ring.nbf + 1, ring.nbf + 1), dtype=torch.float64, device="cuda"))
+
+
+def test_batched_energy_finite_differences():
+    """Screened all-quartet plan (density form with degeneracy weights):
+    central differences of the GPU energy against the GPU gradient."""
+    from paper_2303_13632_amd import eri
+    sh = W.molecule_basis(n_heavy=1, n_h=3, lattice=(2, 2, 1), seed=W.SEED_BASE + 46)
+    plan = eri.Plan(sh, None, bits=0, schwarz=0.0)
+    D = torch.tensor(W.random_density(plan.nbf, seed=46), device="cuda")
+    gc, ge, _ = plan.backward(density=D)
+    gc, ge = gc.cpu().numpy().reshape(-1), ge.cpu().numpy()
+    scale = max(np.abs(gc).max(), np.abs(ge).max())
+
+    def energy(s2):
+        p2 = eri.Plan(s2, None, bits=0, schwarz=0.0)
+        _, _, en = p2.backward(density=D, energy_only=True)
+        return en.item()
+
+    def fd(key, idx, h):
+        def at(d):
+            s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
+            s2[key].reshape(-1)[idx] += d
+            return energy(s2)
+        d1 = (at(h) - at(-h)) / (2 * h)
+        d2 = (at(h / 2) - at(-h / 2)) / h
+        return (4 * d2 - d1) / 3
+
+    rng = np.random.default_rng(46)
+    for idx in rng.choice(len(gc), size=5, replace=False):
+        v = fd("xyz", int(idx), 1e-3)
+        assert abs(v - gc[idx]) <= 1e-7 * scale, ("xyz", idx, v, gc[idx])
+    for idx in rng.choice(len(ge), size=5, replace=False):
+        v = fd("exps", int(idx), 1e-3 * sh["exps"][idx])
+        assert abs(v - ge[idx]) <= 1e-7 * scale, ("exps", idx, v, ge[idx])
