@@ -71,6 +71,11 @@ def main():
     ap.add_argument("--classes", default="all", help="'all' or comma-separated class ids")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch variants (no autotuning)")
+    ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices")
+    ap.add_argument("--secondary", default="mixed,gradient",
+                    help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
+                         "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
@@ -89,22 +94,68 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2303_13632_amd import eri
+    import torch  # noqa: F401
+    from paper_2303_13632_amd import eri  # noqa: F401
 
     if args.workload == "molecule":
-        return bench_molecule(args)
+        print(json.dumps(bench_molecule(args)), flush=True)
+        return
     if args.workload == "gradient":
-        return bench_gradient(args)
+        print(json.dumps(bench_gradient(args)), flush=True)
+        return
     classes = list(range(256)) if args.classes == "all" else [int(c) for c in args.classes.split(",")]
+    res = bench_classes(args, classes, args.precision, args.bits, args.steps, args.warmup, args.per_class_out)
+    out = {
+        "metric": METRIC, "value": res["geris"], "unit": "GERIS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": res["config"],
+        "whole_step_tflops": res["whole_step_tflops"],
+        "tuned": res["tuned"], "tune_s": res["tune_s"],
+        "roofline": res["roofline"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(res["active"], args.cpu_seconds)
+    sec = [x for x in args.secondary.split(",") if x and x != "none"]
+    if sec:
+        out["secondary"] = {}
+    if "mixed" in sec and args.precision == "fp64":
+        m = bench_classes(args, classes, "mixed", args.bits, max(1, args.steps // 2), 1, "")
+        out["secondary"]["fp32_mixed"] = {
+            "value": m["geris"], "unit": "GERIS", "ms_per_step": m["ms_per_step"], "tuned": m["tuned"],
+            "note": "same workload; FP32 VRR/HRR, FP64 Boys/prefactor/accumulation; the 1e-7 Ha accuracy target "
+                    "is not met by every class (reported by tests/test_gpu_mixed.py)",
+            "roofline_class": m["roofline"]["class"], "roofline_frac": m["roofline"]["frac"]}
+    if "gradient" in sec:
+        g = bench_gradient(args, steps=1, warmup=1)
+        out["secondary"]["fwd_grad"] = {k: g[k] for k in ("value", "unit", "ms_per_step", "forward_ms", "adjoint_ms",
+                                                          "forward_geris", "adjoint_geris")}
+        out["secondary"]["fwd_grad"]["workload"] = g["config"]["workload"]
+        out["secondary"]["fwd_grad"]["n_eri"] = g["config"]["n_eri"]
+    print(json.dumps(out), flush=True)
+
+
+def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
+    """The 256-class workload: all classes once per step (HIP events around
+    every class launch on the launch stream)."""
+    import torch
+    from paper_2303_13632_amd import eri
+    from paper_2303_13632_amd import workloads as W
     t0 = time.time()
     shells, quartets = build_workload(args.quartets_per_class, classes)
     log("workload: %d quartets, %d shells (%.1fs)" % (len(quartets), len(shells["L"]), time.time() - t0))
     t0 = time.time()
-    plan = eri.Plan(shells, quartets, precision=args.precision, bits=args.bits, device=0)
+    plan = eri.Plan(shells, quartets, precision=precision, bits=bits, device=0)
     del shells, quartets
-    log("plan: %d ERIs, %d primitive quartets, %.1f GB on device (%.1fs)"
-        % (plan.n_eri, plan.n_prim_quartets, plan.device_bytes / 1e9, time.time() - t0))
+    log("plan %s: %d ERIs, %d primitive quartets, %.1f GB on device (%.1fs)"
+        % (precision, plan.n_eri, plan.n_prim_quartets, plan.device_bytes / 1e9, time.time() - t0))
+    tune_s = 0.0
+    if not args.no_tune:
+        t0 = time.time()
+        plan.tune(sample_quartets=args.quartets_per_class, trials=2, cache=args.tune_cache or None)
+        tune_s = time.time() - t0
+        log("tuned in %.1fs: %d classes off the default variant" % (tune_s, int((plan.class_variant > 0).sum())))
     _, codes, scales = plan.alloc(eri=False, codes=True)
     stream = torch.cuda.current_stream()
     active = [c for c in classes if plan.class_quartets[c] > 0]
@@ -117,61 +168,56 @@ def main():
             if events is not None:
                 events[i][1].record(stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in active]
-          for _ in range(args.steps)]
+          for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step(ev[k])
         log("step %d done" % k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = wall * 1e3 / args.steps
+    ms_step = wall * 1e3 / steps
     per_class_ms = np.array([[ev[k][i][0].elapsed_time(ev[k][i][1]) for i in range(len(active))]
-                             for k in range(args.steps)]).mean(axis=0)
+                             for k in range(steps)]).mean(axis=0)
     geris = plan.n_eri / (ms_step / 1e3) / 1e9
-
     # roofline of the dominant kernel (the class with the largest time per step)
     dom = int(np.argmax(per_class_ms))
     c_dom = active[dom]
     t_dom = per_class_ms[dom] / 1e3
     achieved = plan.class_flops[c_dom] / t_dom / 1e12
-    peak = PEAK_TFLOPS[args.precision]
-    from paper_2303_13632_amd import workloads as W
+    peak = PEAK_TFLOPS[precision]
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": "eri_%s_c%03d" % (args.precision, c_dom),
+            "traffic": None, "kernel": plan.kernel_name(c_dom),
             "class": "[%d%d|%d%d]" % W.class_of(c_dom), "avg_ms": per_class_ms[dom],
             "algorithmic_flops_per_launch": plan.class_flops[c_dom]}
     total_flops = float(sum(plan.class_flops[c] for c in active))
-    if args.per_class_out:
+    if per_class_out:
         rows = []
         for i, c in enumerate(active):
             n_eri_c = int(plan.class_eri_off[c + 1] - plan.class_eri_off[c])
             rows.append({"class": c, "L": W.class_of(c), "ms": per_class_ms[i], "n_eri": n_eri_c,
                          "geris": n_eri_c / (per_class_ms[i] / 1e3) / 1e9,
-                         "tflops": plan.class_flops[c] / (per_class_ms[i] / 1e3) / 1e12})
-        with open(args.per_class_out, "w") as f:
+                         "tflops": plan.class_flops[c] / (per_class_ms[i] / 1e3) / 1e12,
+                         "kernel": plan.kernel_name(c), "variant": int(plan.class_variant[c]),
+                         "block": int(plan.class_block[c])})
+        with open(per_class_out, "w") as f:
             json.dump(rows, f, indent=1)
-
-    out = {
-        "metric": METRIC, "value": geris, "unit": "GERIS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
-                               "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, int%d per-quartet compression"
-                               % (len(active), args.quartets_per_class, args.precision, args.bits),
-                   "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
-                   "n_prim_quartets": int(plan.n_prim_quartets), "precision": args.precision, "bits": args.bits},
-        "whole_step_tflops": total_flops / (ms_step / 1e3) / 1e12,
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(active, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    config = {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
+                          "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, int%d per-quartet compression"
+                          % (len(active), args.quartets_per_class, precision, bits),
+              "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
+              "n_prim_quartets": int(plan.n_prim_quartets), "precision": precision, "bits": bits}
+    res = {"geris": geris, "ms_per_step": ms_step, "config": config, "roofline": roof,
+           "whole_step_tflops": total_flops / (ms_step / 1e3) / 1e12, "active": active,
+           "tuned": not args.no_tune, "tune_s": tune_s}
+    del codes, scales
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_molecule(args):
@@ -216,10 +262,10 @@ def bench_molecule(args):
                    "n_eri": int(plan.n_eri), "n_prim_quartets": int(plan.n_prim_quartets)},
         "whole_step_tflops": flops / (ms_step / 1e3) / 1e12,
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def bench_gradient(args):
+def bench_gradient(args, steps=None, warmup=None):
     """Forward + adjoint on the 64-atom basis (22 heavy + 42 H on a 4x4x4
     lattice, s-d shells): every unique Schwarz-screened quartet computed with
     int16 codes (one graph launch), then E = sum D D (ab|cd) with the
@@ -253,24 +299,26 @@ def bench_gradient(args):
         if ev:
             ev[3].record(stream)
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     t0 = time.time()
-    for _ in range(max(1, args.warmup)):
+    for _ in range(max(1, warmup)):
         step()
     torch.cuda.synchronize()
     log("warmup (incl. derived tables) %.1fs" % (time.time() - t0))
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
     t0 = time.perf_counter()
-    for k in range(args.steps):
+    for k in range(steps):
         step(evs[k])
         log("step %d done" % k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fwd = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     bwd = float(np.mean([e[2].elapsed_time(e[3]) for e in evs]))
-    ms_step = wall * 1e3 / args.steps
+    ms_step = wall * 1e3 / steps
     out = {
         "metric": METRIC, "value": plan.n_eri / (ms_step / 1e3) / 1e9, "unit": "GERIS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "steps": steps, "warmup": warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "adjoint: 64-atom basis (22 heavy s,s,s,p,p,d K 1-6 + 42 H s,s,p; 4x4x4 jittered "
                                "3.5 Bohr lattice), all unique quartets with Q_ab Q_cd >= %g; forward with int%d "
@@ -284,7 +332,7 @@ def bench_gradient(args):
     }
     if args.fd_sample > 0:
         out["fd_check"] = fd_check(sh, D, gc.cpu().numpy(), ge.cpu().numpy(), args)
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def fd_check(sh, D, gc, ge, args, h=1e-4):
@@ -301,19 +349,27 @@ def fd_check(sh, D, gc, ge, args, h=1e-4):
         _, _, en = p2.backward(density=D, energy_only=True)
         return float(en.item())
 
+    def central(key, idx, step):
+        vals = []
+        for d in (step, -step):
+            s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
+            s2[key].reshape(-1)[idx] += d
+            vals.append(energy(s2))
+        return (vals[0] - vals[1]) / (2 * step)
+
     rows = []
     for key, n_all, g in (("xyz", 3 * len(sh["L"]), gc.reshape(-1)), ("exps", len(sh["exps"]), ge)):
         for idx in rng.choice(n_all, size=min(args.fd_sample, n_all), replace=False):
-            vals = []
-            for d in (h, -h):
-                s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
-                s2[key].reshape(-1)[idx] += d
-                vals.append(energy(s2))
-            fd = (vals[0] - vals[1]) / (2 * h)
-            rel = abs(fd - g[idx]) / max(abs(fd), 1e-8 * gmax)
-            rows.append({"param": key, "index": int(idx), "analytic": float(g[idx]), "fd": fd, "rel": rel})
+            fd = central(key, idx, h)
+            # Richardson extrapolation from steps 10h and 5h: O(h^4) truncation
+            # with ten times less rounding noise than the plain h difference
+            rich = (4 * central(key, idx, 5 * h) - central(key, idx, 10 * h)) / 3
+            rows.append({"param": key, "index": int(idx), "analytic": float(g[idx]), "fd": fd, "fd_richardson": rich,
+                         "rel": abs(fd - g[idx]) / max(abs(fd), 1e-8 * gmax),
+                         "rel_richardson": abs(rich - g[idx]) / max(abs(rich), 1e-8 * gmax)})
         log("fd %s done" % key)
     return {"h": h, "n": len(rows), "max_rel": max(r["rel"] for r in rows),
+            "max_rel_richardson": max(r["rel_richardson"] for r in rows),
             "max_abs_over_gmax": max(abs(r["fd"] - r["analytic"]) for r in rows) / gmax,
             "worst": max(rows, key=lambda r: r["rel"])}
 

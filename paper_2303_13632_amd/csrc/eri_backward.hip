@@ -72,6 +72,7 @@ struct eri_bwd_state {
     int64_t scratch_elems = 0;
     int kmax[BWD_MAXL + 1] = {};  // largest K among shells of each L
     int kmax_all = 1;
+    bool full = false;            // derived records built (else energy only)
     int32_t* d_cnt = nullptr;     // per quartet of a pass: primitives of the differentiated shell
     int32_t* d_off = nullptr;     // their exclusive prefix sums
     int32_t* d_origin = nullptr;  // exponent items: quartet | (primitive << 24)
@@ -375,7 +376,8 @@ bool stored_reversed(const shell_set& s, int32_t x, int32_t y, bool by_score)
     return by_score && x != y && vrr_score(s, y, x) < vrr_score(s, x, y);
 }
 
-int build_state(eri_plan* p, eri_bwd_state*& out)
+// full = false builds only the base records (energy-only calls).
+int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
 {
     eri_bwd_state* st = new (std::nothrow) eri_bwd_state();
     if (!st) return ERI_ENOMEM;
@@ -416,6 +418,9 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
         }
     }
     const int64_t nb = (int64_t)base_keys.size();
+    for (int64_t s = 0; s < ns; ++s)
+        if (orig.L[s] <= BWD_MAXL) st->kmax[orig.L[s]] = std::max(st->kmax[orig.L[s]], (int)orig.K[s]);
+    st->full = full;
     // ---- derived shells ------------------------------------------------------
     ext_shells ex;
     ex.L.assign(orig.L, orig.L + ns);
@@ -425,7 +430,7 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
     ex.exps = p->sh_exps;
     ex.coefs = p->sh_coefs;
     std::vector<int32_t> plus(ns), minus(ns, -1), e0(ns), e2(ns);
-    for (int64_t s = 0; s < ns; ++s) {
+    for (int64_t s = 0; s < ns && full; ++s) {
         const int L = orig.L[s], K = orig.K[s];
         const double* c3 = orig.xyz + 3 * s;
         const double* al = orig.exps + orig.off[s];
@@ -447,7 +452,6 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
             const int32_t id = ex.add(L + 2, c3, 1, al + k, &v);
             if (k == 0) e2[s] = id;
         }
-        if (L <= BWD_MAXL) st->kmax[L] = std::max(st->kmax[L], K);
     }
     const shell_set es = ex.view();
     // ---- derived pair keys and the map --------------------------------------
@@ -455,7 +459,9 @@ int build_state(eri_plan* p, eri_bwd_state*& out)
     std::vector<int32_t> dmap(8 * nb, 0);
     std::vector<int32_t> null_slots;   // dmap entries to point at the null record
     auto key = [](int32_t x, int32_t y) { return ((uint64_t)(uint32_t)x << 32) | (uint32_t)y; };
-    for (int64_t i = 0; i < nb; ++i) {
+    for (int64_t i = 0; i < nb && !full; ++i)
+        for (int q = 0; q < 8; ++q) null_slots.push_back((int32_t)(8 * i + q));
+    for (int64_t i = 0; i < nb && full; ++i) {
         const int32_t sa = (int32_t)(base_keys[i] >> 32), sb = (int32_t)(base_keys[i] & 0xffffffffu);
         for (int side = 0; side < 2; ++side) {
             const int32_t s = side ? sb : sa, o = side ? sa : sb;
@@ -718,9 +724,13 @@ extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, co
     ERI_HIP_TRY(hipGetDevice(&cur));
     if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
     int rc = ERI_OK;
+    if (p->bwd && grad_centers && !p->bwd->full) {
+        eri_bwd_free(p->bwd);
+        p->bwd = nullptr;
+    }
     if (!p->bwd) {
         try {
-            rc = build_state(p, p->bwd);
+            rc = build_state(p, p->bwd, grad_centers != nullptr);
         } catch (const std::bad_alloc&) {
             rc = ERI_ENOMEM;
         }
