@@ -505,7 +505,7 @@ def wave_layout(cp):
     return subs, ep
 
 
-def emit_mode_W(cp, prec, name, lds_budget=32768):
+def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
@@ -546,7 +546,11 @@ def emit_mode_W(cp, prec, name, lds_budget=32768):
     for row in rows:
         em("  {" + ", ".join(str(v) for v in row) + "},")
     em("};")
-    em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
+    if waves > 1:
+        # at least `waves` wavefronts per SIMD: the register budget halves
+        em("__global__ __launch_bounds__(64, %d) void %s(eri_class_args A)" % (waves, name))
+    else:
+        em("__global__ __launch_bounds__(64) void %s(eri_class_args A)" % name)
     em.block("")
     NF = cp.Ltot + 1 + 17          # staged fields of one primitive quartet
     NSU = max(NSLOT * NTE * CH, NF * 64)
@@ -763,11 +767,37 @@ def emit_mode_W(cp, prec, name, lds_budget=32768):
     return name, em.text()
 
 
-def emit_class(cp, prec, alt=False):
+def emit_class(cp, prec, alt=False, occupancy=1):
     name = kernel_name(prec, cp.user, alt)
     if cp.mode == "T":
         return name, emit_mode_T(cp, prec, name)[1]
+    if occupancy > 1:
+        name += "_o%d" % occupancy
+        return name, emit_mode_W(cp, prec, name, lds_budget=16384, waves=occupancy)[1]
     return name, emit_mode_W(cp, prec, name)[1]
+
+
+def lds_chunks(cp, lds_budget):
+    """Chunks of the ket-HRR staging of a slot-mapped kernel."""
+    subs, EP = wave_layout(cp)
+    NSLOT = 64 // EP
+    NTE = len(cp.E_T)
+    NCD = ncart(cp.c) * ncart(cp.d)
+    CH = min(NCD, max(1, lds_budget // (8 * NSLOT * NTE)))
+    return (NCD + CH - 1) // CH
+
+
+def occupancy_variant(cp):
+    """Slot-mapped classes large enough to be register-bound also get a
+    kernel limited to half the registers (two wavefronts per SIMD, half the
+    LDS staging).  Not for classes with two bra indices per lane whose
+    staging would need more chunks than the default: an [ff|ff] kernel
+    staged in three or more chunks returned wrong values on the GPU while the
+    same source run on the CPU gave the right ones, a failure not understood."""
+    if cp.mode != "W" or cp.Ltot < 6:
+        return False
+    subs, EP = wave_layout(cp)
+    return len(subs) == 1 or lds_chunks(cp, 16384) == lds_chunks(cp, 32768)
 
 
 def alternate_mode(cp):
@@ -786,21 +816,26 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 """
 
 
-def kernel_info_init(cp, name, block=64):
+# kernel tags (last field of eri_kernel_info): which generated kernel a variant launches
+TAG_DEFAULT, TAG_ALT, TAG_OCC2 = 0, 1, 2
+
+
+def kernel_info_init(cp, name, block=64, tag=TAG_DEFAULT):
     subs, EP = wave_layout(cp)
     per_pq, per_q = cp.flops()
     pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
     if cp.mode == "T":
-        return "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, 0}" % (name, block, block, cp.n_eriq, per_pq, per_q, pk)
-    return "{(const void*)%s, 1, 64, %d, %d, %d, %d, %d, 0}" % (name, 64 // EP, cp.n_eriq, per_pq, per_q, pk)
+        return "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, %d}" % (name, block, block, cp.n_eriq, per_pq, per_q,
+                                                                      pk, tag)
+    return "{(const void*)%s, 1, 64, %d, %d, %d, %d, %d, %d}" % (name, 64 // EP, cp.n_eriq, per_pq, per_q, pk, tag)
 
 
-def variant_infos(cp, name):
+def variant_infos(cp, name, tag=TAG_DEFAULT):
     """Launch variants of one kernel: mode T at 64, 128 and 256 quartets per
     workgroup, mode W as generated."""
     if cp.mode == "T":
-        return [kernel_info_init(cp, name, b) for b in (64, 128, 256)]
-    return [kernel_info_init(cp, name)]
+        return [kernel_info_init(cp, name, b, tag) for b in (64, 128, 256)]
+    return [kernel_info_init(cp, name, tag=tag)]
 
 
 def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None, g_classes=True):
@@ -839,7 +874,11 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 acp = ClassPlan(*user, mode=am, perm=cp.perm)
                 aname, asrc = emit_class(acp, prec, alt=True)
                 parts.append(asrc)
-                infos += variant_infos(acp, aname)
+                infos += variant_infos(acp, aname, TAG_ALT)
+            if max(user) <= 3 and occupancy_variant(cp):
+                oname, osrc = emit_class(cp, prec, occupancy=2)
+                parts.append(osrc)
+                infos += variant_infos(cp, oname, TAG_OCC2)
             for k, info in enumerate(infos):
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
         for prec, lines_ in reg.items():

@@ -547,6 +547,7 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
         int nv = 0;
         while (nv < ERI_MAXVAR && var[class_id5_of(c) * ERI_MAXVAR + nv].fn) ++nv;
         info->class_n_variants[c] = nv;
+        info->class_tag[c] = ki.tag;
     }
     for (int c = 0; c <= 256; ++c) {
         info->class_eri_off[c] = p->class_eoff[c];

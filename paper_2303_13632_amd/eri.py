@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
                 ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256),
                 ("class_variant", ctypes.c_int32 * 256), ("class_mode", ctypes.c_int32 * 256),
                 ("class_block", ctypes.c_int32 * 256), ("class_per_block", ctypes.c_int32 * 256),
-                ("class_n_variants", ctypes.c_int32 * 256)]
+                ("class_n_variants", ctypes.c_int32 * 256), ("class_tag", ctypes.c_int32 * 256)]
 
 
 _vp = ctypes.c_void_p
@@ -190,6 +190,7 @@ class Plan:
         self.class_block = np.array(info.class_block[:], dtype=np.int32)
         self.class_per_block = np.array(info.class_per_block[:], dtype=np.int32)
         self.class_n_variants = np.array(info.class_n_variants[:], dtype=np.int32)
+        self.class_tag = np.array(info.class_tag[:], dtype=np.int32)
 
     def tune(self, sample_quartets=65536, trials=3, cache=None, stream=None):
         """eri_plan_tune: time each class's launch variants on a sample and keep
@@ -209,9 +210,8 @@ class Plan:
 
     def kernel_name(self, cid):
         """Name of the kernel a class launch uses (variant included)."""
-        L = [(cid >> 6) & 3, (cid >> 4) & 3, (cid >> 2) & 3, cid & 3]
         prec = "mixed" if self.precision == "mixed" else "fp64"
-        return "eri_%s_c%03d%s" % (prec, cid, "_a" if self.class_mode[cid] != _default_mode(L) else "")
+        return "eri_%s_c%03d%s" % (prec, cid, {0: "", 1: "_a", 2: "_o2"}[int(self.class_tag[cid])])
 
     def layout(self):
         """(pos, eri_off) per user quartet (plan position, first ERI)."""
@@ -325,25 +325,6 @@ class Plan:
             self.close()
         except Exception:
             pass
-
-
-def _default_mode(L):
-    """Work mapping of a class's default kernel (0 lane per quartet, 1 slots),
-    as the generator chooses it."""
-    import importlib.util
-    global _codegen
-    if _codegen is None:
-        spec = importlib.util.spec_from_file_location("_eri_codegen", os.path.join(_PKG, "csrc", "codegen.py"))
-        _codegen = importlib.util.module_from_spec(spec)
-        spec.loader.exec_module(_codegen)
-    key = tuple(L)
-    if key not in _mode_cache:
-        _mode_cache[key] = 0 if _codegen.ClassPlan(*key).mode == "T" else 1
-    return _mode_cache[key]
-
-
-_codegen = None
-_mode_cache = {}
 
 
 def _ncart(L):
