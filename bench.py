@@ -52,7 +52,7 @@ def cpu_baseline(classes, seconds):
         return time.perf_counter() - t0, int(sizes.sum()), len(q)
 
     t, neri, nq = run(1)
-    n = max(1, min(512, int(seconds / max(t, 1e-3))))
+    n = max(1, min(8192, int(seconds / max(t, 1e-3))))
     if n > 1:
         t, neri, nq = run(n)
     return {"value": neri / t / 1e9, "unit": "GERIS", "cores": threads, "kind": "oracle",
@@ -77,7 +77,7 @@ def main():
                     help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
                          "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
-    ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient"],
+    ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
                          "unique quartet of the 384-atom molecule-like basis in one graph launch; "
                          "gradient: E = sum D D (ab|cd) and its gradient on the 64-atom basis")
@@ -102,6 +102,9 @@ def main():
         return
     if args.workload == "gradient":
         print(json.dumps(bench_gradient(args)), flush=True)
+        return
+    if args.workload == "copy":
+        print(json.dumps(bench_copy(args)), flush=True)
         return
     classes = list(range(256)) if args.classes == "all" else [int(c) for c in args.classes.split(",")]
     res = bench_classes(args, classes, args.precision, args.bits, args.steps, args.warmup, args.per_class_out)
@@ -218,6 +221,20 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
     plan.close()
     torch.cuda.empty_cache()
     return res
+
+
+def bench_copy(args):
+    """A plain 1 GiB device-to-device copy, the reference for scaling the
+    FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 1 << 27
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(max(1, args.steps)):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    return {"workload": "copy", "bytes_read_per_launch": 8 * n, "bytes_written_per_launch": 8 * n,
+            "launches": max(1, args.steps)}
 
 
 def bench_molecule(args):
