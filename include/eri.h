@@ -97,7 +97,8 @@ typedef struct {
     int32_t class_per_block[256]; /* its quartets per workgroup */
     int32_t class_n_variants[256];/* launch variants available: 0 .. n-1 */
     int32_t class_tag[256];       /* kernel of the variant in use: 0 default, 1 alternate mapping
-                                     (name suffix _a), 2 half-register slots (suffix _o2) */
+                                     (name suffix _a), 2 half-register slots (suffix _o2),
+                                     3 two-wavefront slots (suffix _w2) */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
@@ -158,7 +159,9 @@ int eri_compute_class(eri_plan* plan, int32_t class_id, void* stream, double* ou
  * mapping at 64, 128 or 256 quartets per workgroup (one lane per quartet),
  * an alternate mapping (a slot of lanes per quartet instead of one lane, or
  * the reverse) and, for large slot-mapped classes, a kernel limited to half
- * the registers (two wavefronts per SIMD, half the LDS staging).  For every
+ * the registers (two wavefronts per SIMD, half the LDS staging) or, where a
+ * lane would hold two bra indices, a kernel that spreads them over two
+ * wavefronts.  For every
  * class of the plan with more than one variant,
  * the first min(class_quartets, sample_quartets) quartets are computed with
  * each variant `trials` times on `stream` (outputs to scratch memory the call

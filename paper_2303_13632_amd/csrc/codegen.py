@@ -767,6 +767,243 @@ def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     return name, em.text()
 
 
+def emit_mode_W2(cp, prec, name, lds_budget=32768):
+    """Two-subslot classes (|e| <= 6, 84 bra indices) on two wavefronts: wave
+    w holds the bra indices of parity w, one per lane, so a lane carries one
+    set of accumulators instead of two.  The ket VRR's coupling term comes
+    from the other parity, i.e. the other wave: each ket level's values are
+    exchanged through LDS (double-buffered by level parity), one barrier per
+    level.  Primitive quartets are staged 64 at a time by the first wave."""
+    real = REALS[prec]
+    mixed = prec == "mixed"
+    em = Emitter()
+    a, b, c, d = cp.a, cp.b, cp.c, cp.d
+    subs, EP = wave_layout(cp)
+    assert len(subs) == 2
+    E_T = cp.E_T
+    tgt_index = {e: k for k, e in enumerate(E_T)}
+    NTE = len(E_T)
+    ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
+    NCD = len(cc) * len(cd)
+    CH = min(NCD, max(1, lds_budget // (8 * NTE)))
+    NCH = (NCD + CH - 1) // CH
+    Lcd = cp.Lcd
+    # per wave and lane: ex, ey, ez, valid, tgt, src_x, src_y, src_z (src: lane of
+    # e - 1_i in the other wave)
+    rows = []
+    for w in range(2):
+        other = subs[1 - w]
+        for ls in range(64):
+            if ls < len(subs[w]):
+                e = subs[w][ls]
+                src = [other.index(vsub(e, UNIT[i])) if e[i] >= 1 else ls for i in range(3)]
+                rows.append([e[0], e[1], e[2], 1, tgt_index.get(e, -1)] + src)
+            else:
+                rows.append([0, 0, 0, 0, -1, ls, ls, ls])
+    tbl = "eri_tbl_" + name[4:]
+    em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode W on two waves (%d + %d lanes), %s"
+       % (cp.user + (cp.perm, a, b, c, d, len(subs[0]), len(subs[1]), prec)))
+    em("static __constant__ signed char %s[128][8] = {" % tbl)
+    for row in rows:
+        em("  {" + ", ".join(str(v) for v in row) + "},")
+    em("};")
+    # exchange slots of one level: values (f, m) with |f| = L - 1, 1 <= m <= Lcd - L + 1
+    xidx = {}
+    NX = 1
+    for L in range(1, Lcd + 1):
+        k = 0
+        for fp in comps(L - 1):
+            for m in range(1, Lcd - L + 2):
+                xidx[(L, fp, m)] = k
+                k += 1
+        NX = max(NX, k)
+    NF = cp.Ltot + 1 + 17
+    NSU = max(NTE * CH, NF * 64)
+    em("__global__ __launch_bounds__(128) void %s(eri_class_args A)" % name)
+    em.block("")
+    em("__shared__ double s_u[%d];" % NSU)
+    em("__shared__ double s_x[2][2][%d][64];   // [level parity][wave][value][lane]" % NX)
+    em("__shared__ double s_red[128];")
+    em("double (*s_t)[%d] = reinterpret_cast<double (*)[%d]>(s_u);" % (CH, CH))
+    em("const int tid = threadIdx.x;")
+    em("const int wv = tid >> 6;")
+    em("const int ls = tid & 63;")
+    em("const int64_t qi = blockIdx.x;")
+    em("const bool active = qi < A.n_items;")
+    em("const eri_item it = A.items[active ? qi : 0];")
+    em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
+    em("const eri_shell_pair BP = A.pairs[it.bra & 0x7fffffff];")
+    em("const eri_shell_pair KP = A.pairs[it.ket & 0x7fffffff];")
+    em("const int nbra = active ? BP.nprim : 0;")
+    em("const int nket = KP.nprim;")
+    em("const int ex0 = %s[tid][0], ey0 = %s[tid][1], ez0 = %s[tid][2];" % (tbl, tbl, tbl))
+    em("const int tg0 = %s[tid][4];" % tbl)
+    em("const int sx0 = %s[tid][5], sy0 = %s[tid][6], sz0 = %s[tid][7];" % (tbl, tbl, tbl))
+    acc = {}
+    for f in cp.F_T:
+        acc[f] = "acc_%d%d%d" % f
+        em("double %s = 0.0;" % acc[f])
+    em("const int npq = nbra * nket;   // one quartet per workgroup: uniform")
+    em.block("for (int j0 = 0; j0 < npq; j0 += 64)")
+    em("__syncthreads();")
+    em.block("if (wv == 0)")
+    em("double g[%d];" % NF)
+    em("#pragma unroll")
+    em("for (int q = 0; q < %d; ++q) g[q] = 0.0;" % NF)
+    em("const int j = j0 + ls;")
+    em.block("if (j < npq)")
+    em("const int ib = j / nket, ik = j - ib * nket;")
+    em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
+    em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
+    em("eri_pq_fp64 S;")
+    em("eri_pq_setup(B, K, S);")
+    em("double F[%d];" % (cp.Ltot + 1))
+    em("eri_boys<%d>(S.T, F);" % cp.Ltot)
+    em("#pragma unroll")
+    em("for (int m = 0; m <= %d; ++m) g[m] = S.pref * F[m];" % cp.Ltot)
+    o = cp.Ltot + 1
+    fields = ["B.PA[0]", "B.PA[1]", "B.PA[2]", "S.WP[0]", "S.WP[1]", "S.WP[2]",
+              "K.PA[0]", "K.PA[1]", "K.PA[2]", "S.WQ[0]", "S.WQ[1]", "S.WQ[2]",
+              "B.hp", "K.hp", "S.hpq", "S.rho_p", "S.rho_q"]
+    for k, fld in enumerate(fields):
+        em("g[%d] = %s;" % (o + k, fld))
+    em.end()
+    em("#pragma unroll")
+    em("for (int q = 0; q < %d; ++q) s_u[q * 64 + ls] = g[q];" % NF)
+    em.end()
+    em("__syncthreads();")
+    em("const int nb = min(64, npq - j0);")
+    em.block("for (int jj = 0; jj < nb; ++jj)")
+    em("const double* u = s_u + jj;")
+    names = ["PAx", "PAy", "PAz", "WPx", "WPy", "WPz", "QCx", "QCy", "QCz", "WQx", "WQy", "WQz",
+             "hp", "hq", "hpq", "rp", "rq"]
+    for k, nm in enumerate(names):
+        em("const %s %s = (%s)u[%d];" % (real, nm, real, 64 * (o + k)))
+    MB = cp.Ltot
+    em("%s c0[%d], p0[%d], nx0[%d];" % (real, MB + 2, MB + 2, MB + 2))
+    em("#pragma unroll")
+    em("for (int m = 0; m <= %d; ++m) { c0[m] = (%s)u[64 * m]; p0[m] = (%s)0; }" % (MB, real, real))
+    em("const %s cex0 = (%s)ex0 * hpq, cey0 = (%s)ey0 * hpq, cez0 = (%s)ez0 * hpq;" % (real, real, real, real))
+    for t in range(1, cp.Lab + 1):
+        M = cp.Lcd + cp.Lab - t
+        em.block("")
+        em("const bool iz = %d <= ez0;" % t)
+        em("const bool iy = !iz && %d <= ez0 + ey0;" % t)
+        em("const bool ix = !iz && !iy && %d <= ez0 + ey0 + ex0;" % t)
+        em("const int nt = iz ? %d : iy ? %d - ez0 : ix ? %d - ez0 - ey0 : 0;" % (t - 1, t - 1, t - 1))
+        em("const %s pa = iz ? PAz : iy ? PAy : ix ? PAx : (%s)1;" % (real, real))
+        em("const %s wp = iz ? WPz : iy ? WPy : ix ? WPx : (%s)0;" % (real, real))
+        em("const %s cc = (%s)nt * hp;" % (real, real))
+        em("#pragma unroll")
+        em("for (int m = 0; m <= %d; ++m) nx0[m] = pa * c0[m] + wp * c0[m + 1] + cc * (p0[m] - rp * p0[m + 1]);" % M)
+        em("#pragma unroll")
+        em("for (int m = 0; m <= %d; ++m) { p0[m] = c0[m]; c0[m] = nx0[m]; }" % M)
+        em.end()
+    # ket VRR by levels; the coupling term of level L reads the other wave's
+    # level L - 1 values from LDS
+    V = {}
+    for m in range(Lcd + 1):
+        V[(ZERO, m)] = "c0[%d]" % m
+    tset = set(cp.F_T)
+    if ZERO in tset:
+        em("%s += %s;" % (acc[ZERO], ("(double)" + V[(ZERO, 0)]) if mixed else V[(ZERO, 0)]))
+    nvar = 0
+    for L in range(1, Lcd + 1):
+        par = L & 1
+        for fp in comps(L - 1):
+            for m in range(1, Lcd - L + 2):
+                em("s_x[%d][wv][%d][ls] = (double)%s;" % (par, xidx[(L, fp, m)], V[(fp, m)]))
+        em("__syncthreads();")
+        for f in comps(L):
+            i = 0 if f[0] > 0 else (1 if f[1] > 0 else 2)
+            ax = "xyz"[i]
+            fp = vsub(f, UNIT[i])
+            for m in range(Lcd - L + 1):
+                nm = "w%d" % nvar
+                nvar += 1
+                expr = "QC%s * %s + WQ%s * %s" % (ax, V[(fp, m)], ax, V[(fp, m + 1)])
+                if fp[i] >= 1:
+                    fpp = vsub(fp, UNIT[i])
+                    expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), V[(fpp, m)], V[(fpp, m + 1)])
+                expr += " + ce%s0 * (%s)s_x[%d][wv ^ 1][%d][s%s0]" % (ax, real, par, xidx[(L, fp, m + 1)], ax)
+                em("const %s %s = %s;" % (real, nm, expr))
+                V[(f, m)] = nm
+            if f in tset:
+                v = V[(f, 0)]
+                em("%s += %s;" % (acc[f], ("(double)" + v) if mixed else v))
+    em.end()
+    em.end()
+    # HRR: ket per lane into s_t rows, bra over all 128 threads
+    emit_slot(em, "qi")
+    em("const int64_t obase = oslot * %d;" % cp.n_eriq)
+    emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
+    emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
+    cd_list = [(ci, di) for ci in cc for di in cd]
+    ab_list = [(ai, bi) for ai in ca for bi in cb]
+
+    def ket_hrr_chunk(ch):
+        lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
+        em("__syncthreads();")
+        em.block("if (active && tg0 >= 0)")
+        for k in range(lo, hi):
+            ci, di = cd_list[k]
+            expr = hrr_expr(di, ci, lambda f: "(%s)%s" % (real, acc[f]), "cd")
+            em("s_t[tg0][%d] = (double)(%s);" % (k - lo, expr))
+        em.end()
+        em("__syncthreads();")
+
+    def bra_hrr_chunk(ch, pass_no):
+        lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
+        n = hi - lo
+        em.block("for (int j = tid; j < %d; j += 128)" % n)
+        em.block("if (active)")
+        em("const int kcd = %d + j;" % lo)
+        for k, (ai, bi) in enumerate(ab_list):
+            expr = hrr_expr(bi, ai, lambda e: "(%s)s_t[%d][j]" % (real, tgt_index[e]), "ab")
+            em("const double x%d = (double)(%s);" % (k, expr))
+        st = user_strides(cp)
+        nd = len(cd)
+        kn = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[2], nd, st[3])
+        if st[2] == nd * st[3] and st[3] == 1:
+            kn = "(int64_t)kcd"
+        if cp.c == cp.d and nd > 1:
+            ks = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[3], nd, st[2])
+            em("const int64_t kx = sk ? %s : %s;" % (ks, kn))
+        else:
+            em("const int64_t kx = %s;" % kn)
+        for k in range(len(ab_list)):
+            ia_, ib_ = divmod(k, len(cb))
+            bra, _ = index_parts(cp, ia_, ib_, 0, 0)
+            ix = "%s + kx" % bra
+            if pass_no == 1:
+                em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                em("bmax = fmax(bmax, fabs(x%d));" % k)
+            else:
+                em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
+        em.end()
+        em.end()
+
+    em("double bmax = 0.0;")
+    for ch in range(NCH):
+        ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 1)
+    em("__syncthreads();")
+    em("s_red[tid] = bmax;")
+    em("__syncthreads();")
+    em.block("if (A.out_codes)")
+    em("double m = 0.0;")
+    em("for (int k = 0; k < 128; ++k) m = fmax(m, s_red[k]);")
+    em("const double eps = m * A.cn;")
+    em("const double inv = eri_inverse_scale(eps);")
+    em("if (active && tid == 0 && A.out_scales) A.out_scales[oslot] = eps;")
+    for ch in range(NCH):
+        ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 2)
+    em.end()
+    em.end()
+    return name, em.text()
+
+
 def emit_class(cp, prec, alt=False, occupancy=1):
     name = kernel_name(prec, cp.user, alt)
     if cp.mode == "T":
@@ -817,7 +1054,7 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 
 
 # kernel tags (last field of eri_kernel_info): which generated kernel a variant launches
-TAG_DEFAULT, TAG_ALT, TAG_OCC2 = 0, 1, 2
+TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES = 0, 1, 2, 3
 
 
 def kernel_info_init(cp, name, block=64, tag=TAG_DEFAULT):
@@ -879,6 +1116,14 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 oname, osrc = emit_class(cp, prec, occupancy=2)
                 parts.append(osrc)
                 infos += variant_infos(cp, oname, TAG_OCC2)
+            if max(user) <= 3 and cp.mode == "W" and len(wave_layout(cp)[0]) == 2 and cp.Lcd >= 2:
+                wname = kernel_name(prec, cp.user) + "_w2"
+                wname, wsrc = emit_mode_W2(cp, prec, wname)
+                parts.append(wsrc)
+                per_pq, per_q = cp.flops()
+                pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
+                infos.append("{(const void*)%s, 1, 128, 1, %d, %d, %d, %d, %d}"
+                             % (wname, cp.n_eriq, per_pq, per_q, pk, TAG_TWO_WAVES))
             for k, info in enumerate(infos):
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
         for prec, lines_ in reg.items():
