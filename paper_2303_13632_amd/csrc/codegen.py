@@ -772,8 +772,10 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768):
     w holds the bra indices of parity w, one per lane, so a lane carries one
     set of accumulators instead of two.  The ket VRR's coupling term comes
     from the other parity, i.e. the other wave: each ket level's values are
-    exchanged through LDS (double-buffered by level parity), one barrier per
-    level.  Primitive quartets are staged 64 at a time by the first wave."""
+    exchanged through LDS, with a barrier before and after each level's
+    reads.  Primitive quartets are staged 64 at a time by the first wave.
+    One LDS pool holds the staging and the exchange during the recurrences,
+    then the HRR staging, so two workgroups fit on a CU."""
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
@@ -818,11 +820,12 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768):
                 k += 1
         NX = max(NX, k)
     NF = cp.Ltot + 1 + 17
-    NSU = max(NTE * CH, NF * 64)
+    NSU = max(NTE * CH, NF * 64 + 2 * NX * 64)
     em("__global__ __launch_bounds__(128) void %s(eri_class_args A)" % name)
     em.block("")
     em("__shared__ double s_u[%d];" % NSU)
-    em("__shared__ double s_x[2][2][%d][64];   // [level parity][wave][value][lane]" % NX)
+    em("double (*s_x)[%d][64] = reinterpret_cast<double (*)[%d][64]>(s_u + %d);   // [wave][value][lane]"
+       % (NX, NX, NF * 64))
     em("__shared__ double s_red[128];")
     em("double (*s_t)[%d] = reinterpret_cast<double (*)[%d]>(s_u);" % (CH, CH))
     em("const int tid = threadIdx.x;")
@@ -909,10 +912,10 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768):
         em("%s += %s;" % (acc[ZERO], ("(double)" + V[(ZERO, 0)]) if mixed else V[(ZERO, 0)]))
     nvar = 0
     for L in range(1, Lcd + 1):
-        par = L & 1
+        em("__syncthreads();   // the other wave has read the previous exchange")
         for fp in comps(L - 1):
             for m in range(1, Lcd - L + 2):
-                em("s_x[%d][wv][%d][ls] = (double)%s;" % (par, xidx[(L, fp, m)], V[(fp, m)]))
+                em("s_x[wv][%d][ls] = (double)%s;" % (xidx[(L, fp, m)], V[(fp, m)]))
         em("__syncthreads();")
         for f in comps(L):
             i = 0 if f[0] > 0 else (1 if f[1] > 0 else 2)
@@ -925,7 +928,7 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768):
                 if fp[i] >= 1:
                     fpp = vsub(fp, UNIT[i])
                     expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), V[(fpp, m)], V[(fpp, m + 1)])
-                expr += " + ce%s0 * (%s)s_x[%d][wv ^ 1][%d][s%s0]" % (ax, real, par, xidx[(L, fp, m + 1)], ax)
+                expr += " + ce%s0 * (%s)s_x[wv ^ 1][%d][s%s0]" % (ax, real, xidx[(L, fp, m + 1)], ax)
                 em("const %s %s = %s;" % (real, nm, expr))
                 V[(f, m)] = nm
             if f in tset:
