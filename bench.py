@@ -73,8 +73,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variants (no autotuning)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices")
-    ap.add_argument("--secondary", default="mixed,gradient",
+    ap.add_argument("--secondary", default="mixed,int12,gradient",
                     help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
+                         "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
                          "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy"],
@@ -130,6 +131,8 @@ def main():
             "note": "same workload; FP32 VRR/HRR, FP64 Boys/prefactor/accumulation; the 1e-7 Ha accuracy target "
                     "is not met by every class (reported by tests/test_gpu_mixed.py)",
             "roofline_class": m["roofline"]["class"], "roofline_frac": m["roofline"]["frac"]}
+    if "int12" in sec:
+        out["secondary"]["int12_packed"] = bench_packed(args, classes, 12)
     if "gradient" in sec:
         g = bench_gradient(args, steps=1, warmup=1)
         out["secondary"]["fwd_grad"] = {k: g[k] for k in ("value", "unit", "ms_per_step", "forward_ms", "adjoint_ms",
@@ -137,6 +140,80 @@ def main():
         out["secondary"]["fwd_grad"]["workload"] = g["config"]["workload"]
         out["secondary"]["fwd_grad"]["n_eri"] = g["config"]["n_eri"]
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes summarised in profiles/<kernel>_traffic.md, or None
+    when there is no summary or it was taken with another build of the
+    library (the kernel may have changed since)."""
+    import hashlib
+    from paper_2303_13632_amd import eri
+    path = os.path.join(ROOT, "profiles", "%s_traffic.md" % kernel)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    with open(eri.LIB_PATH, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    if fields.get("liberi_hip.so sha1") != sha:
+        return None
+    return float(fields["fetch bytes per launch"]) + float(fields["write bytes per launch"])
+
+
+def bench_packed(args, classes, bits):
+    """The 256-class workload with n-bit codes (int16 containers from the
+    fused kernels) packed into the 512-bit word stream; a step is every class
+    launch plus the pack kernel, timed by HIP events on the launch stream."""
+    import torch
+    from paper_2303_13632_amd import eri
+    shells, quartets = build_workload(args.quartets_per_class, classes)
+    plan = eri.Plan(shells, quartets, precision="fp64", bits=bits, device=0)
+    del shells, quartets
+    if not args.no_tune:
+        plan.tune(sample_quartets=args.quartets_per_class, trials=2, cache=args.tune_cache or None)
+    _, codes, scales = plan.alloc(eri=False, codes=True)
+    off = []
+    for c in range(256):
+        n = int(plan.class_quartets[c])
+        if n:
+            m = int((plan.class_eri_off[c + 1] - plan.class_eri_off[c]) // n)
+            off.append(plan.class_eri_off[c] + m * np.arange(n, dtype=np.int64))
+    off = np.concatenate(off + [np.array([plan.n_eri], dtype=np.int64)])
+    woff = eri.packed_word_offsets(bits, off)
+    d_off = torch.tensor(off, device="cuda")
+    d_woff = torch.tensor(woff, device="cuda")
+    packed = torch.empty(8 * int(woff[-1]), dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    plan.compute(None, codes, scales, stream=stream)
+    eri.pack(bits, codes, d_off, d_woff, packed, stream=stream)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    comp = pack_ms = 0.0
+    for _ in range(steps):
+        e0.record(stream)
+        plan.compute(None, codes, scales, stream=stream)
+        e1.record(stream)
+        eri.pack(bits, codes, d_off, d_woff, packed, stream=stream)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        comp += e0.elapsed_time(e1)
+        pack_ms += e1.elapsed_time(e2)
+    comp /= steps
+    pack_ms /= steps
+    res = {"value": plan.n_eri / ((comp + pack_ms) / 1e3) / 1e9, "unit": "GERIS", "bits": bits,
+           "ms_per_step": comp + pack_ms, "pack_ms": pack_ms,
+           "packed_bytes": int(woff[-1]) * 64, "int16_container_bytes": int(plan.n_eri) * 2,
+           "note": "same workload; codes computed into int16 containers, then packed into 512-bit words of "
+                   "floor(512/n) codes with every quartet word-aligned"}
+    del codes, scales, packed
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
@@ -194,7 +271,8 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
     achieved = plan.class_flops[c_dom] / t_dom / 1e12
     peak = PEAK_TFLOPS[precision]
     roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": None, "kernel": plan.kernel_name(c_dom),
+            "traffic": measured_traffic(plan.kernel_name(c_dom)), "traffic_unit": "HBM bytes per launch",
+            "kernel": plan.kernel_name(c_dom),
             "class": "[%d%d|%d%d]" % W.class_of(c_dom), "avg_ms": per_class_ms[dom],
             "algorithmic_flops_per_launch": plan.class_flops[c_dom]}
     total_flops = float(sum(plan.class_flops[c] for c in active))
@@ -250,6 +328,12 @@ def bench_molecule(args):
                     ring_bytes=int(args.ring_gb * 1e9))
     log("plan: %d atoms, %d shells, %d screened quartets, %d ERIs, %d primitive quartets (%.1fs)"
         % (n_heavy + n_h, len(sh["L"]), plan.n_quartets, plan.n_eri, plan.n_prim_quartets, time.time() - t0))
+    tune_s = 0.0
+    if not args.no_tune:
+        t0 = time.time()
+        plan.tune(sample_quartets=65536, trials=2, cache=args.tune_cache or None)
+        tune_s = time.time() - t0
+        log("tuned in %.1fs: %d classes off the default variant" % (tune_s, int((plan.class_variant > 0).sum())))
     _, codes, scales = plan.alloc(eri=False, codes=True)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
@@ -277,7 +361,7 @@ def bench_molecule(args):
                                % (n_heavy, n_h, args.schwarz, args.bits, args.ring_gb),
                    "n_shells": int(len(sh["L"])), "n_quartets": int(plan.n_quartets),
                    "n_eri": int(plan.n_eri), "n_prim_quartets": int(plan.n_prim_quartets)},
-        "whole_step_tflops": flops / (ms_step / 1e3) / 1e12,
+        "whole_step_tflops": flops / (ms_step / 1e3) / 1e12, "tuned": not args.no_tune, "tune_s": tune_s,
     }
     return out
 

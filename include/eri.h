@@ -222,6 +222,25 @@ int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_
 int eri_backward(eri_plan* plan, void* stream, const double* dl_deri, const double* density, int64_t nbf,
                  double* grad_centers, double* grad_exps, double* energy);
 
+/* Packed code stream for an arbitrary width n (Sec. III-B: the output is
+ * streamed as 512-bit words holding floor(512/n) codes each, and every
+ * quartet starts on a new word).  Block b's codes (the container array of
+ * eri_compress: int8/int16/int32 for n <= 8/16/32, entries
+ * block_off[b] .. block_off[b+1]) go to 64-byte words word_off[b] ..
+ * word_off[b+1] - 1, where word_off[b+1] - word_off[b] =
+ * ceil(size_b / floor(512/n)); code k of a block sits in word k / per at
+ * bits (k mod per) * n .. + n - 1 (little-endian across the word's eight
+ * 64-bit lanes), as its n low two's-complement bits; unused bits are zero.
+ * block_off, word_off: device int64, n_blocks + 1 entries; packed: device,
+ * n_words * 64 bytes.  ERI_EUNSUPPORTED for n outside [2, 32]. */
+int eri_pack(int32_t bits, const void* codes, int64_t n_blocks, const int64_t* block_off,
+             const int64_t* word_off, int64_t n_words, void* packed, void* stream);
+
+/* Reverse of eri_pack: writes int32 codes (codes, optional) and/or the
+ * decompressed values code * scales[b] (eq. 11; out, optional, needs scales). */
+int eri_unpack(int32_t bits, const void* packed, int64_t n_blocks, const int64_t* block_off,
+               const int64_t* word_off, const double* scales, int32_t* codes, double* out, void* stream);
+
 void eri_plan_destroy(eri_plan* plan);
 
 const char* eri_status_string(int status);

@@ -16,6 +16,8 @@ from .oracle import (  # noqa: F401
     compress,
     decompress,
     gradient,
+    pack,
+    unpack,
     ncart,
     components,
 )

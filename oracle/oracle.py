@@ -214,3 +214,55 @@ def gradient(shells, quartets, weights=None, dl=None, density=None, n_threads=No
     if rc != 0:
         raise ValueError("oracle_gradient: bad arguments (rc=%d)" % rc)
     return float(en[0]), gx.reshape(-1, 3), ge[:len(exps)]
+
+
+def pack(bits, codes, block_off):
+    """Packed stream of n-bit codes: 512-bit words of floor(512/n) codes,
+    every block (quartet) starting on a new word; code k of a block sits in
+    word k // per at bit (k % per) * n of the word (bit 0 = least significant
+    bit of the word's first byte), as its n low two's-complement bits.
+    Returns (uint8 array of 64-byte words, word offset of each block)."""
+    bits = int(bits)
+    per = 512 // bits
+    codes = np.asarray(codes, dtype=np.int64)
+    block_off = np.asarray(block_off, dtype=np.int64)
+    sizes = np.diff(block_off)
+    word_off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    word_off[1:] = np.cumsum((sizes + per - 1) // per)
+    out = np.zeros(int(word_off[-1]) * 64, dtype=np.uint8)
+    mask = (1 << bits) - 1
+    for b in range(len(sizes)):
+        for k in range(int(sizes[b])):
+            v = int(codes[block_off[b] + k]) & mask
+            w = int(word_off[b]) + k // per
+            pos = (k % per) * bits
+            for t in range(bits):
+                if (v >> t) & 1:
+                    bit = pos + t
+                    out[64 * w + bit // 8] |= np.uint8(1 << (bit % 8))
+    return out, word_off
+
+
+def unpack(bits, packed, block_off):
+    """Inverse of pack(): int64 codes, sign-extended from n bits."""
+    bits = int(bits)
+    per = 512 // bits
+    block_off = np.asarray(block_off, dtype=np.int64)
+    sizes = np.diff(block_off)
+    word_off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    word_off[1:] = np.cumsum((sizes + per - 1) // per)
+    packed = np.asarray(packed, dtype=np.uint8)
+    out = np.zeros(int(block_off[-1]) if len(block_off) else 0, dtype=np.int64)
+    for b in range(len(sizes)):
+        for k in range(int(sizes[b])):
+            w = int(word_off[b]) + k // per
+            pos = (k % per) * bits
+            v = 0
+            for t in range(bits):
+                bit = pos + t
+                if (int(packed[64 * w + bit // 8]) >> (bit % 8)) & 1:
+                    v |= 1 << t
+            if v >> (bits - 1):
+                v -= 1 << bits
+            out[block_off[b] + k] = v
+    return out

@@ -81,6 +81,7 @@ struct eri_bwd_state {
     int64_t n_grad = 0;           // 3 n_shells + n_prims + 1 (energy)
     double* d_part = nullptr;     // BWD_SLICES partial gradients (LDS mode)
     int32_t* h_pin = nullptr;     // pinned host word for scan totals
+    std::vector<int8_t> var = std::vector<int8_t>(ERI_NCLASS5, -1);   // launch variant per derived class
 };
 
 void eri_bwd_free(eri_bwd_state* b)
@@ -579,6 +580,55 @@ struct bwd_call {
     bool lds;
 };
 
+// Launch variant of a derived class: the first pass that meets the class
+// times each variant once on up to 65536 of its items (after a warm-up
+// launch) and keeps the fastest for the rest of the plan's life.
+static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, hipStream_t strm,
+                        const eri_kernel_info*& out)
+{
+    const eri_kernel_info* var = eri_kernel_variants(0) + (int64_t)c5 * ERI_MAXVAR;
+    if (st->var[c5] >= 0) {
+        out = &var[st->var[c5]];
+        return ERI_OK;
+    }
+    int nv = 0;
+    while (nv < ERI_MAXVAR && var[nv].fn) ++nv;
+    int best = 0;
+    if (nv > 1) {
+        eri_class_args a = full;
+        a.n_items = std::min<int64_t>(full.n_items, 65536);
+        a.ring = a.n_items;
+        hipEvent_t e0, e1;
+        ERI_HIP_TRY(hipEventCreate(&e0));
+        ERI_HIP_TRY(hipEventCreate(&e1));
+        float best_ms = 0.f;
+        int rc = ERI_OK;
+        for (int k = 0; k < nv && rc == ERI_OK; ++k) {
+            const int64_t grid = (a.n_items + var[k].per_block - 1) / var[k].per_block;
+            void* args[] = {&a};
+            float ms = 0.f;
+            for (int t = 0; t < 2; ++t) {
+                if (t == 1 && hipEventRecord(e0, strm) != hipSuccess) rc = ERI_EHIP;
+                if (hipLaunchKernel(var[k].fn, dim3((unsigned)grid), dim3(var[k].block), args, 0, strm) != hipSuccess)
+                    rc = ERI_EHIP;
+            }
+            if (rc == ERI_OK && (hipEventRecord(e1, strm) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                rc = ERI_EHIP;
+            if (rc == ERI_OK && (k == 0 || ms < best_ms)) {
+                best_ms = ms;
+                best = k;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != ERI_OK) return rc;
+    }
+    st->var[c5] = (int8_t)best;
+    out = &var[best];
+    return ERI_OK;
+}
+
 // One derived kind over `m` items: derive, forward kernel of the derived
 // class into scratch, contraction.
 static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const eri_item* uitems, int64_t m,
@@ -605,10 +655,12 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     a.out_eri = st->d_scratch;
     a.ring = m;
     a.qbase = 0;
-    const int64_t grid = (m + ki.per_block - 1) / ki.per_block;
+    const eri_kernel_info* kv = &ki;
+    ERI_TRY(pick_variant(st, class_id5(Lp[0], Lp[1], Lp[2], Lp[3]), a, strm, kv));
+    const int64_t grid = (m + kv->per_block - 1) / kv->per_block;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     void* args[] = {&a};
-    ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, strm));
+    ERI_HIP_TRY(hipLaunchKernel(kv->fn, dim3((unsigned)grid), dim3(kv->block), args, 0, strm));
     bwd_contract_args ca;
     std::memset(&ca, 0, sizeof(ca));
     ca.uitems = uitems;

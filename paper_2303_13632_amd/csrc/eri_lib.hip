@@ -998,6 +998,103 @@ extern "C" int eri_decompress(int32_t bits, const void* codes, const double* sca
     return ERI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Packed code stream: 512-bit words of floor(512 / n) n-bit codes, each block
+// (quartet) starting on a word.  One thread per word.
+// ---------------------------------------------------------------------------
+template <typename CT>
+__global__ __launch_bounds__(256) void eri_pack_kernel(const CT* __restrict__ codes, const int64_t* __restrict__ off,
+                                                       const int64_t* __restrict__ woff, int64_t n_blocks,
+                                                       int64_t n_words, int bits, uint64_t* __restrict__ packed)
+{
+    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (w >= n_words) return;
+    // block owning word w: last b with woff[b] <= w
+    int64_t lo = 0, hi = n_blocks;
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (woff[mid] <= w) lo = mid; else hi = mid;
+    }
+    const int per = 512 / bits;
+    const int64_t first = off[lo] + (w - woff[lo]) * per;
+    const int64_t end = off[lo + 1];
+    const uint64_t mask = bits == 64 ? ~0ull : ((1ull << bits) - 1ull);
+    uint64_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < per && first + k < end; ++k) {
+        const uint64_t v = (uint64_t)(int64_t)codes[first + k] & mask;
+        const int bit = k * bits;
+        const int q = bit >> 6, r = bit & 63;
+        out[q] |= v << r;
+        if (r + bits > 64) out[q + 1] |= v >> (64 - r);
+    }
+    for (int q = 0; q < 8; ++q) packed[8 * w + q] = out[q];
+}
+
+// Decode: one thread per code; sign-extends the n-bit field.
+__device__ __forceinline__ int32_t eri_packed_code(const uint64_t* __restrict__ packed, int64_t word, int k, int bits)
+{
+    const int bit = k * bits;
+    const int q = bit >> 6, r = bit & 63;
+    uint64_t v = packed[8 * word + q] >> r;
+    if (r + bits > 64) v |= packed[8 * word + q + 1] << (64 - r);
+    const int sh = 64 - bits;
+    return (int32_t)((int64_t)(v << sh) >> sh);
+}
+
+__global__ __launch_bounds__(256) void eri_unpack_kernel(const uint64_t* __restrict__ packed,
+                                                         const int64_t* __restrict__ off,
+                                                         const int64_t* __restrict__ woff, const double* __restrict__ scales,
+                                                         int64_t n_blocks, int bits, int32_t* __restrict__ codes,
+                                                         double* __restrict__ out)
+{
+    const int64_t b = blockIdx.x;
+    if (b >= n_blocks) return;
+    const int per = 512 / bits;
+    const int64_t lo = off[b], n = off[b + 1] - lo;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const int32_t q = eri_packed_code(packed, woff[b] + i / per, (int)(i % per), bits);
+        if (codes) codes[lo + i] = q;
+        if (out) out[lo + i] = (double)q * scales[b];
+    }
+}
+
+extern "C" int eri_pack(int32_t bits, const void* codes, int64_t n_blocks, const int64_t* block_off,
+                        const int64_t* word_off, int64_t n_words, void* packed, void* stream)
+{
+    if (bits < 2 || bits > 32) return ERI_EUNSUPPORTED;
+    if (n_blocks < 0 || n_words < 0 || (n_words > 0 && (!codes || !block_off || !word_off || !packed)))
+        return ERI_EINVAL;
+    if (n_words == 0 || n_blocks == 0) return ERI_OK;
+    const int64_t grid = (n_words + 255) / 256;
+    if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    if (bits <= 8)
+        hipLaunchKernelGGL(eri_pack_kernel<int8_t>, dim3((unsigned)grid), dim3(256), 0, st, (const int8_t*)codes,
+                           block_off, word_off, n_blocks, n_words, bits, (uint64_t*)packed);
+    else if (bits <= 16)
+        hipLaunchKernelGGL(eri_pack_kernel<int16_t>, dim3((unsigned)grid), dim3(256), 0, st, (const int16_t*)codes,
+                           block_off, word_off, n_blocks, n_words, bits, (uint64_t*)packed);
+    else
+        hipLaunchKernelGGL(eri_pack_kernel<int32_t>, dim3((unsigned)grid), dim3(256), 0, st, (const int32_t*)codes,
+                           block_off, word_off, n_blocks, n_words, bits, (uint64_t*)packed);
+    ERI_HIP_TRY(hipGetLastError());
+    return ERI_OK;
+}
+
+extern "C" int eri_unpack(int32_t bits, const void* packed, int64_t n_blocks, const int64_t* block_off,
+                          const int64_t* word_off, const double* scales, int32_t* codes, double* out, void* stream)
+{
+    if (bits < 2 || bits > 32) return ERI_EUNSUPPORTED;
+    if (n_blocks < 0 || (n_blocks > 0 && (!packed || !block_off || !word_off || (!codes && !out) || (out && !scales))))
+        return ERI_EINVAL;
+    if (n_blocks == 0) return ERI_OK;
+    if (n_blocks > INT32_MAX) return ERI_EUNSUPPORTED;
+    hipLaunchKernelGGL(eri_unpack_kernel, dim3((unsigned)n_blocks), dim3(256), 0, (hipStream_t)stream,
+                       (const uint64_t*)packed, block_off, word_off, scales, n_blocks, bits, codes, out);
+    ERI_HIP_TRY(hipGetLastError());
+    return ERI_OK;
+}
+
 extern "C" void eri_plan_destroy(eri_plan* p) { plan_free(p); }
 
 extern "C" const char* eri_status_string(int s)

@@ -86,6 +86,8 @@ def load():
     lib.eri_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eri_plan_tune.argtypes = [_vp, _vp, ctypes.c_int64, ctypes.c_int32, ctypes.c_char_p]
     lib.eri_plan_set_variants.argtypes = [_vp, _i32p]
+    lib.eri_pack.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
+    lib.eri_unpack.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.eri_plan_destroy.argtypes = [_vp]
     lib.eri_plan_destroy.restype = None
     lib.eri_status_string.argtypes = [ctypes.c_int]
@@ -413,3 +415,37 @@ def __getattr__(name):
             _autograd = _make_autograd()
         return _autograd[0] if name == "ERIFunction" else _autograd[1]
     raise AttributeError(name)
+
+
+def packed_word_offsets(bits, block_off):
+    """First 512-bit word of every block (n_blocks + 1 entries, host numpy):
+    ceil(size / floor(512 / bits)) words per block."""
+    per = 512 // int(bits)
+    sizes = np.diff(np.asarray(block_off, dtype=np.int64))
+    w = np.zeros(len(sizes) + 1, dtype=np.int64)
+    w[1:] = np.cumsum((sizes + per - 1) // per)
+    return w
+
+
+def pack(bits, codes, block_off, word_off, packed=None, stream=None):
+    """eri_pack on device tensors (block_off, word_off: device int64)."""
+    import torch
+    nb = block_off.numel() - 1
+    n_words = int(word_off[-1].item()) if word_off.numel() else 0
+    if packed is None:
+        packed = torch.zeros(max(8 * n_words, 8), dtype=torch.int64, device=codes.device)
+    _check(load().eri_pack(int(bits), _ptr(codes), nb, _ptr(block_off), _ptr(word_off), n_words, _ptr(packed),
+                           _stream(stream)), "eri_pack")
+    return packed
+
+
+def unpack(bits, packed, block_off, word_off, scales=None, codes=True, values=False, stream=None):
+    """eri_unpack: returns (int32 codes or None, decompressed values or None)."""
+    import torch
+    nb = block_off.numel() - 1
+    n = int(block_off[-1].item()) if block_off.numel() else 0
+    c = torch.empty(max(n, 1), dtype=torch.int32, device=packed.device) if codes else None
+    v = torch.empty(max(n, 1), dtype=torch.float64, device=packed.device) if values else None
+    _check(load().eri_unpack(int(bits), _ptr(packed), nb, _ptr(block_off), _ptr(word_off), _ptr(scales), _ptr(c),
+                             _ptr(v), _stream(stream)), "eri_unpack")
+    return c, v
