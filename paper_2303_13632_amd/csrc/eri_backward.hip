@@ -82,13 +82,18 @@ struct eri_bwd_state {
     double* d_part = nullptr;     // BWD_SLICES partial gradients (LDS mode)
     int32_t* h_pin = nullptr;     // pinned host word for scan totals
     std::vector<int8_t> var = std::vector<int8_t>(ERI_NCLASS5, -1);   // launch variant per derived class
+    eri_item* d_usorted = nullptr;   // a pass's user items ordered by primitive-quartet count
+    int32_t* d_key = nullptr;        // sort keys / values (4 arrays of chunk_cap)
+    void* d_sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
 };
 
 void eri_bwd_free(eri_bwd_state* b)
 {
     if (!b) return;
-    void* ptrs[] = {b->d_pairs, b->d_prims, b->d_dmap,   b->d_uall,     b->d_uitems, b->d_ditems, b->d_scratch,
-                    b->d_bf,    b->d_poff,  b->d_cnt,    b->d_off,      b->d_origin, b->d_scan_tmp, b->d_part};
+    void* ptrs[] = {b->d_pairs,  b->d_prims, b->d_dmap,   b->d_uall,     b->d_uitems,   b->d_ditems,
+                    b->d_scratch, b->d_bf,    b->d_poff,   b->d_cnt,      b->d_off,      b->d_origin,
+                    b->d_scan_tmp, b->d_part, b->d_usorted, b->d_key,     b->d_sort_tmp};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     if (b->h_pin) (void)hipHostFree(b->h_pin);
@@ -158,6 +163,28 @@ __global__ __launch_bounds__(256) void eri_bwd_derive_kernel(const eri_item* __r
     out[j] = o;
 }
 
+// Sort key of a user item: its primitive-quartet count (capped to 16 bits).
+__global__ __launch_bounds__(256) void eri_bwd_key_kernel(const eri_item* __restrict__ uitems, int64_t n,
+                                                          const eri_shell_pair* __restrict__ pairs,
+                                                          int32_t* __restrict__ key, int32_t* __restrict__ idx)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const eri_item u = uitems[i];
+    const int npq = pairs[u.bra & 0x7fffffff].nprim * pairs[u.ket & 0x7fffffff].nprim;
+    key[i] = npq < 65535 ? npq : 65535;
+    idx[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void eri_bwd_gather_kernel(const eri_item* __restrict__ uitems, int64_t n,
+                                                             const int32_t* __restrict__ idx,
+                                                             eri_item* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    out[i] = uitems[idx[i]];
+}
+
 // Primitive count of the shell at user position `pos` of each quartet.
 __global__ __launch_bounds__(256) void eri_bwd_count_kernel(const eri_item* __restrict__ uitems, int64_t n,
                                                             const eri_shell_pair* __restrict__ pairs, int pos,
@@ -209,6 +236,7 @@ struct bwd_contract_args {
     const eri_item* uitems;
     int64_t n;                  // items (derived blocks)
     const int32_t* origin;      // exponent kinds: item -> quartet | (primitive << 24); else null
+    const int32_t* orig;        // quartet -> its index in the pass (plan order), for dl
     const eri_shell_pair* pairs;
     const double* blk;          // derived blocks, one per item
     const double* dl;           // dL/dERI in plan layout, or null
@@ -286,7 +314,7 @@ __global__ __launch_bounds__(256) void eri_bwd_contract_kernel(bwd_contract_args
             ci[0] = rem;
             double g;
             if (A.dl) {
-                g = A.dl[A.dl_base + i * n_eriq + o];
+                g = A.dl[A.dl_base + (int64_t)A.orig[i] * n_eriq + o];
             } else {
                 g = A.dens[(f0 + ci[0]) * A.nbf + f1 + ci[1]] * A.dens[(f2 + ci[2]) * A.nbf + f3 + ci[3]];
             }
@@ -545,6 +573,18 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
         }
     }
     up((void**)&st->d_scan_tmp, nullptr, std::max<size_t>(st->scan_tmp_bytes, 64));
+    if (p->batched == false) up((void**)&st->d_uitems, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
+    up((void**)&st->d_usorted, nullptr, (size_t)st->chunk_cap * sizeof(eri_item));
+    up((void**)&st->d_key, nullptr, (size_t)st->chunk_cap * 4 * sizeof(int32_t));
+    if (rc == ERI_OK) {
+        hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, st->sort_tmp_bytes, st->d_key, st->d_key, st->d_key,
+                                                          st->d_key, (int)st->chunk_cap, 0, 16, (hipStream_t)0);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            rc = ERI_EHIP;
+        }
+    }
+    up((void**)&st->d_sort_tmp, nullptr, std::max<size_t>(st->sort_tmp_bytes, 64));
     if (st->n_grad <= BWD_LDS_MAX) up((void**)&st->d_part, nullptr, (size_t)BWD_SLICES * st->n_grad * sizeof(double));
     if (rc == ERI_OK) {
         hipError_t e = hipHostMalloc((void**)&st->h_pin, 2 * sizeof(int32_t), hipHostMallocDefault);
@@ -632,7 +672,7 @@ static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, h
 // One derived kind over `m` items: derive, forward kernel of the derived
 // class into scratch, contraction.
 static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const eri_item* uitems, int64_t m,
-                    const int32_t* origin, int pos, int kind, int64_t q0, const bwd_call& call)
+                    const int32_t* origin, const int32_t* orig, int pos, int kind, int64_t q0, const bwd_call& call)
 {
     if (m == 0) return ERI_OK;
     const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
@@ -666,6 +706,7 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     ca.uitems = uitems;
     ca.n = m;
     ca.origin = origin;
+    ca.orig = orig;
     ca.pairs = st->d_pairs;
     ca.blk = st->d_scratch;
     ca.dl = call.dl;
@@ -729,11 +770,26 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd
         } else {
             uitems = st->d_uall + p->class_qoff[c] + q0;
         }
-        if (call.energy) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, 0, DK_BASE, q0, call));
+        // order the pass by primitive-quartet count, so that the lanes of a
+        // wavefront (and the slots of a workgroup) loop over similar counts
+        const unsigned gm = (unsigned)((m + 255) / 256);
+        int32_t* key_in = st->d_key;
+        int32_t* idx_in = st->d_key + st->chunk_cap;
+        int32_t* key_out = st->d_key + 2 * st->chunk_cap;
+        int32_t* orig = st->d_key + 3 * st->chunk_cap;
+        hipLaunchKernelGGL(eri_bwd_key_kernel, dim3(gm), dim3(256), 0, strm, uitems, m, st->d_pairs, key_in, idx_in);
+        ERI_HIP_TRY(hipGetLastError());
+        size_t tmp = st->sort_tmp_bytes;
+        ERI_HIP_TRY(hipcub::DeviceRadixSort::SortPairs(st->d_sort_tmp, tmp, key_in, key_out, idx_in, orig, (int)m, 0,
+                                                       16, strm));
+        hipLaunchKernelGGL(eri_bwd_gather_kernel, dim3(gm), dim3(256), 0, strm, uitems, m, orig, st->d_usorted);
+        ERI_HIP_TRY(hipGetLastError());
+        uitems = st->d_usorted;
+        if (call.energy) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, orig, 0, DK_BASE, q0, call));
         if (!call.grad_c) continue;
         for (int x = 0; x < 3; ++x) {
-            ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, x, DK_PLUS, q0, call));
-            if (L[x] >= 1) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, x, DK_MINUS, q0, call));
+            ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, orig, x, DK_PLUS, q0, call));
+            if (L[x] >= 1) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, orig, x, DK_MINUS, q0, call));
         }
         // exponent kinds: one item per primitive of the shell at position x
         const unsigned g256 = (unsigned)((m + 255) / 256);
@@ -752,8 +808,8 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd
             ERI_HIP_TRY(hipStreamSynchronize(strm));
             const int64_t total = (int64_t)st->h_pin[0] + st->h_pin[1];
             if (total > m * st->kmax_all) return ERI_EHIP;   // cannot happen: K <= kmax
-            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, x, DK_E0, q0, call));
-            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, x, DK_E2, q0, call));
+            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, orig, x, DK_E0, q0, call));
+            ERI_TRY(run_kind(p, st, c, strm, uitems, total, st->d_origin, orig, x, DK_E2, q0, call));
         }
     }
     return ERI_OK;
