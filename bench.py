@@ -78,7 +78,7 @@ def main():
                          "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
                          "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
-    ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy"],
+    ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy", "lattice"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
                          "unique quartet of the 384-atom molecule-like basis in one graph launch; "
                          "gradient: E = sum D D (ab|cd) and its gradient on the 64-atom basis")
@@ -106,6 +106,9 @@ def main():
         return
     if args.workload == "copy":
         print(json.dumps(bench_copy(args)), flush=True)
+        return
+    if args.workload == "lattice":
+        print(json.dumps(bench_lattice(args)), flush=True)
         return
     classes = list(range(256)) if args.classes == "all" else [int(c) for c in args.classes.split(",")]
     res = bench_classes(args, classes, args.precision, args.bits, args.steps, args.warmup, args.per_class_out)
@@ -299,6 +302,87 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
     plan.close()
     torch.cuda.empty_cache()
     return res
+
+
+# the paper's measured FPGA throughput for these classes on this lattice (Table V: one Stratix 10,
+# 16-bit; [ss|ss] and [ff|ds]: two FPGAs, Sec. IV-D), for context
+PAPER_FPGA_GERIS = {"[fd|ps]": 3.33, "[ps|fd]": 1.05, "[ff|dp]": 10.03, "[dp|ff]": 6.65, "[fd|fd]": 11.17,
+                    "[df|fd]": 10.93, "[ss|ss]": 0.08, "[ff|ds]": 15.3}
+PAPER_CLASSES = {"[fd|ps]": (3, 2, 1, 0), "[ps|fd]": (1, 0, 3, 2), "[ff|dp]": (3, 3, 2, 1), "[dp|ff]": (2, 1, 3, 3),
+                 "[fd|fd]": (3, 2, 3, 2), "[df|fd]": (2, 3, 3, 2), "[ss|ss]": (0, 0, 0, 0), "[ff|ds]": (3, 3, 2, 0),
+                 "[ff|ff]": (3, 3, 3, 3)}
+
+
+def bench_lattice(args):
+    """The paper's own benchmark system (Sec. IV-A): 32 sites on a 4x4x2
+    lattice at 1 Angstrom, primitive s, p, d, f shells with exponent 1.5 on
+    every site, no screening.  Per class, every unique site quartet
+    (i >= j, k >= l, ij >= kl; 139656 quartets); all 256 classes per step,
+    with int`bits` codes.  Reports GERIS overall and for the classes the
+    paper tabulates, and the largest quantisation error of the decompressed
+    codes per class (against the GPU FP64 values)."""
+    import torch
+    from paper_2303_13632_amd import eri, workloads as W
+    sh = W.paper_lattice()
+    nsite = len(sh["L"]) // 4
+    pairs = [(i, j) for i in range(nsite) for j in range(i + 1)]
+    site_q = np.array([(p[0], p[1], q[0], q[1]) for a, p in enumerate(pairs) for q in pairs[:a + 1]], dtype=np.int32)
+    quartets = []
+    for cid in range(256):
+        la, lb, lc, ld = (cid >> 6) & 3, (cid >> 4) & 3, (cid >> 2) & 3, cid & 3
+        quartets.append(site_q * 4 + np.array([la, lb, lc, ld], dtype=np.int32))
+    quartets = np.concatenate(quartets)
+    t0 = time.time()
+    plan = eri.Plan(sh, quartets, precision=args.precision, bits=args.bits)
+    log("lattice plan: %d quartets, %d ERIs (%.1fs)" % (plan.n_quartets, plan.n_eri, time.time() - t0))
+    if not args.no_tune:
+        plan.tune(sample_quartets=65536, trials=2)
+    _, codes, scales = plan.alloc(eri=False, codes=True)
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(256)]
+    for _ in range(max(1, args.warmup)):
+        plan.compute(None, codes, scales, stream=stream)
+    torch.cuda.synchronize()
+    per = np.zeros(256)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for c in range(256):
+            ev[c][0].record(stream)
+            plan.compute_class(c, None, codes, scales, stream=stream)
+            ev[c][1].record(stream)
+        torch.cuda.synchronize()
+        per += np.array([ev[c][0].elapsed_time(ev[c][1]) for c in range(256)])
+    wall = (time.perf_counter() - t0) / args.steps
+    per /= args.steps
+    n_eri_c = np.diff(plan.class_eri_off)
+    n_quartets_all, n_eri_all = int(plan.n_quartets), int(plan.n_eri)
+    del codes, scales
+    plan.close()
+    torch.cuda.empty_cache()
+    # quantisation error of the tabulated classes: FP64 values and codes of
+    # one class at a time, decompressed and compared
+    maxerr = {}
+    for name, Lq in PAPER_CLASSES.items():
+        sub = eri.Plan(sh, site_q * 4 + np.array(Lq, dtype=np.int32), precision=args.precision, bits=args.bits)
+        v, cq, sc = sub.alloc(eri=True, codes=True)
+        sub.compute(v, cq, sc)
+        m = int(sub.n_eri // sub.n_quartets)
+        eps = torch.repeat_interleave(sc[: sub.n_quartets], m)
+        maxerr[name] = float((v[: sub.n_eri] - cq[: sub.n_eri].to(torch.float64) * eps).abs().max().item())
+        del v, cq, sc, eps
+        sub.close()
+        torch.cuda.empty_cache()
+    out = {"workload": "paper benchmark lattice: 32 sites 4x4x2 at 1 Angstrom, primitive s,p,d,f (alpha 1.5), "
+                       "139656 unique site quartets per class, all 256 classes, int%d codes, %s" % (args.bits, args.precision),
+           "value": float(n_eri_all / wall / 1e9), "unit": "GERIS", "ms_per_step": wall * 1e3,
+           "n_eri": n_eri_all, "n_quartets": n_quartets_all,
+           "paper_classes": {name: {"geris": float(n_eri_c[c] / (per[c] / 1e3) / 1e9), "ms": float(per[c]),
+                                    "max_abs_quantisation_error": maxerr[name],
+                                    "paper_fpga_geris": PAPER_FPGA_GERIS.get(name)}
+                             for name, Lq in PAPER_CLASSES.items()
+                             for c in [(Lq[0] << 6) | (Lq[1] << 4) | (Lq[2] << 2) | Lq[3]]},
+           "best_class_geris": float(np.max(n_eri_c / (per / 1e3) / 1e9))}
+    return out
 
 
 def bench_copy(args):
