@@ -749,22 +749,33 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd
         maxnd = std::max(maxnd, nd);
     }
     const int64_t chunk = std::max<int64_t>(1, std::min(st->chunk_cap, st->scratch_elems / (maxnd * st->kmax_all)));
-    const eri_batch_class* bc = nullptr;
+    // passes: explicit plans walk the class's plan positions; batched plans
+    // walk each entry of the class (quartet index within the class = qoff + j)
+    struct pass_src {
+        const eri_batch_class* bc;
+        int64_t lo, hi;   // class quartet range
+    };
+    std::vector<pass_src> srcs;
     if (p->batched) {
-        for (auto& b : p->bclass)
-            if (b.cid == c) bc = &b;
-        if (!bc) return ERI_OK;
+        for (const auto& b : p->bclass)
+            if (b.cid == c)
+                for (int64_t q0 = 0; q0 < b.n_quartets; q0 += chunk)
+                    srcs.push_back({&b, b.qoff + q0, b.qoff + std::min(b.n_quartets, q0 + chunk)});
+    } else {
+        for (int64_t q0 = 0; q0 < n; q0 += chunk) srcs.push_back({nullptr, q0, std::min(n, q0 + chunk)});
     }
-    for (int64_t q0 = 0; q0 < n; q0 += chunk) {
-        const int64_t q1 = std::min(n, q0 + chunk), m = q1 - q0;
+    for (const auto& ps : srcs) {
+        const int64_t q0 = ps.lo, m = ps.hi - ps.lo;
         const eri_item* uitems;
-        if (p->batched) {
+        if (ps.bc) {
+            const eri_batch_class* bc = ps.bc;
+            const int64_t e0 = ps.lo - bc->qoff, e1 = ps.hi - bc->qoff;
             const auto sbeg = p->h_seg_off.begin();
-            const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q0) - sbeg) - 1;
-            const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q1) - sbeg);
+            const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, e0) - sbeg) - 1;
+            const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, e1) - sbeg);
             if (s1 - s0 > INT32_MAX) return ERI_EUNSUPPORTED;
             hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, strm, p->d_seg_off,
-                               p->d_seg_p1, s0, bc->ket_lo, q0, q1, 0, st->d_uitems);
+                               p->d_seg_p1, s0, bc->ket_lo, e0, e1, 0, st->d_uitems);
             ERI_HIP_TRY(hipGetLastError());
             uitems = st->d_uitems;
         } else {

@@ -92,15 +92,17 @@ int upload(eri_plan* p, void** dst, const void* src, size_t bytes);
 
 }  // namespace eri_detail
 
-// One batched class: the quartets (P1 | P2) of a bra pair class and a ket
-// pair class, enumerated as segments: for each bra pair P1 a prefix of the
-// Q-sorted ket pair list.
+// One batched entry: the quartets (P1 | P2) of a bra pair group and a ket
+// pair group (pair class and primitive-count bucket), enumerated as
+// segments: for each bra pair P1 a prefix of the Q-sorted ket group.  A class
+// is the concatenation of its entries.
 struct eri_batch_class {
     int cid = -1;
     bool swap = false;              // kernel's computed bra is P2
     int64_t n_quartets = 0;
     int64_t seg_lo = 0, seg_hi = 0; // range in the plan's segment arrays
-    int64_t ket_lo = 0;             // first ket pair (global index) of the ket class
+    int64_t ket_lo = 0;             // first ket pair (global index) of the ket group
+    int64_t qoff = 0;               // index within its class of the entry's first quartet
     int64_t ring = 0;               // output slots
     int64_t chunk = 0;              // quartets per launch (<= ring: no two quartets of
                                     // one launch share a ring slot)

@@ -347,16 +347,24 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
         if (rc != ERI_OK) return rc;
     }
     const double qmax_all = Q.empty() ? 0.0 : *std::max_element(Q.begin(), Q.end());
-    // ---- pair classes (La, Lb), pairs Q-sorted within a class --------------
+    // ---- pair groups: class (La, Lb), then primitive-pair count bucket;
+    //      pairs Q-sorted within a group ----------------------------------
+    // The bucket keeps the primitive-quartet counts of one launch close, so
+    // the lanes and slots of a wavefront loop over similar counts.
     std::vector<int64_t> order;
     for (size_t i = 0; i < keys.size(); ++i)
         if (Q[i] * qmax_all >= p->schwarz && Q[i] > 0.0) order.push_back((int64_t)i);
-    auto pclass = [&](int64_t i) {
+    auto kbucket = [](int nprim) {
+        return nprim <= 1 ? 0 : nprim <= 2 ? 1 : nprim <= 4 ? 2 : nprim <= 6 ? 3 : nprim <= 9 ? 4 : nprim <= 16 ? 5
+                                                                                                   : nprim <= 36 ? 6 : 7;
+    };
+    constexpr int NB = 8;
+    auto group = [&](int64_t i) {
         const int32_t x = (int32_t)(keys[i] >> 32), y = (int32_t)(keys[i] & 0xffffffffu);
-        return s.L[x] * 4 + s.L[y];
+        return (s.L[x] * 4 + s.L[y]) * NB + kbucket(s.K[x] * s.K[y]);
     };
     std::sort(order.begin(), order.end(), [&](int64_t u, int64_t v) {
-        const int cu = pclass(u), cv = pclass(v);
+        const int cu = group(u), cv = group(v);
         if (cu != cv) return cu < cv;
         if (Q[u] != Q[v]) return Q[u] > Q[v];
         return u < v;
@@ -364,80 +372,89 @@ static int create_batched(eri_plan* p, const shell_set& s, const eri_plan_opts* 
     if ((int64_t)order.size() > INT32_MAX) return ERI_EUNSUPPORTED;
     std::vector<uint64_t> skeys(order.size());
     p->pair_q.resize(order.size());
-    int64_t cls_lo[17];
-    for (int c = 0; c <= 16; ++c) cls_lo[c] = 0;
+    std::vector<int64_t> grp_lo(16 * NB + 1, 0);
     for (size_t j = 0; j < order.size(); ++j) {
         skeys[j] = keys[order[j]];
         p->pair_q[j] = Q[order[j]];
-        cls_lo[pclass(order[j]) + 1] += 1;
+        grp_lo[group(order[j]) + 1] += 1;
     }
-    for (int c = 0; c < 16; ++c) cls_lo[c + 1] += cls_lo[c];
+    for (int g = 0; g < 16 * NB; ++g) grp_lo[g + 1] += grp_lo[g];
     std::vector<eri_prim_pair> prims;
     build_pair_tables(s, skeys, p->h_pairs, prims);
     p->n_pairs = (int64_t)p->h_pairs.size();
     p->n_prims = (int64_t)prims.size();
-    // ---- segments: for each bra pair P1, the prefix of ket pairs P2 with
-    //      Q1 Q2 >= tau (and P2 <= P1 inside one pair class) ------------------
+    // ---- segments: for each bra pair P1, the prefix of ket pairs P2 of a
+    //      group with Q1 Q2 >= tau; within one pair class a quartet is kept
+    //      once, as (P1 | P2) with P2 <= P1 in the sorted order --------------
     const int64_t cap = o->chunk_quartets > 0 ? o->chunk_quartets : ((int64_t)1 << 25);
     p->chunk_cap = cap;
     int64_t maxchunk = 1;
     for (int cb = 0; cb < 16; ++cb) {
         for (int ck = 0; ck <= cb; ++ck) {
-            const int64_t b0 = cls_lo[cb], b1 = cls_lo[cb + 1], k0 = cls_lo[ck], k1 = cls_lo[ck + 1];
-            if (b0 == b1 || k0 == k1) continue;
             const int cid = (cb / 4) * 64 + (cb % 4) * 16 + (ck / 4) * 4 + (ck % 4);
-            if (!tab[class_id5_of(cid)].fn) return ERI_EUNSUPPORTED;
-            eri_batch_class bc;
-            bc.cid = cid;
-            bc.swap = (tab[class_id5_of(cid)].perm & 3) >= 2;
-            bc.ket_lo = k0;
-            bc.seg_lo = (int64_t)p->h_seg_p1.size();
-            int64_t q = 0;
-            double flops = 0.0;
-            std::vector<int64_t> kprim(k1 - k0 + 1, 0);
-            for (int64_t k = k0; k < k1; ++k) kprim[k - k0 + 1] = kprim[k - k0] + p->h_pairs[k].nprim;
-            for (int64_t b = b0; b < b1; ++b) {
-                const double need = p->schwarz / p->pair_q[b];
-                // ket pairs are sorted by decreasing Q: count those with Q >= need
-                int64_t lo = k0, hi = k1;
-                while (lo < hi) {
-                    const int64_t mid = (lo + hi) / 2;
-                    if (p->pair_q[mid] >= need) lo = mid + 1; else hi = mid;
+            for (int gb = 0; gb < NB; ++gb) {
+                for (int gk = 0; gk < NB; ++gk) {
+                    if (cb == ck && gk > gb) continue;
+                    const int64_t b0 = grp_lo[cb * NB + gb], b1 = grp_lo[cb * NB + gb + 1];
+                    const int64_t k0 = grp_lo[ck * NB + gk], k1 = grp_lo[ck * NB + gk + 1];
+                    if (b0 == b1 || k0 == k1) continue;
+                    if (!tab[class_id5_of(cid)].fn) return ERI_EUNSUPPORTED;
+                    eri_batch_class bc;
+                    bc.cid = cid;
+                    bc.swap = (tab[class_id5_of(cid)].perm & 3) >= 2;
+                    bc.ket_lo = k0;
+                    bc.qoff = p->class_count[cid];
+                    bc.seg_lo = (int64_t)p->h_seg_p1.size();
+                    int64_t q = 0;
+                    double flops = 0.0;
+                    std::vector<int64_t> kprim(k1 - k0 + 1, 0);
+                    for (int64_t k = k0; k < k1; ++k) kprim[k - k0 + 1] = kprim[k - k0] + p->h_pairs[k].nprim;
+                    for (int64_t b = b0; b < b1; ++b) {
+                        const double need = p->schwarz / p->pair_q[b];
+                        // ket pairs are sorted by decreasing Q: count those with Q >= need
+                        int64_t lo = k0, hi = k1;
+                        while (lo < hi) {
+                            const int64_t mid = (lo + hi) / 2;
+                            if (p->pair_q[mid] >= need) lo = mid + 1; else hi = mid;
+                        }
+                        int64_t n = lo - k0;
+                        if (cb == ck && gb == gk) n = std::min(n, b - b0 + 1);
+                        if (n <= 0) continue;
+                        p->h_seg_off.push_back(q);
+                        p->h_seg_p1.push_back((int32_t)b);
+                        q += n;
+                        const int64_t npq = (int64_t)p->h_pairs[b].nprim * kprim[n];
+                        p->n_prim_quartets += npq;
+                        flops += (double)npq * tab[class_id5_of(cid)].flops_pq + (double)n * tab[class_id5_of(cid)].flops_q;
+                    }
+                    bc.seg_hi = (int64_t)p->h_seg_p1.size();
+                    if (bc.seg_hi == bc.seg_lo) continue;
+                    // closing entry: seg_off[seg_hi] = quartets of this entry
+                    p->h_seg_off.push_back(q);
+                    p->h_seg_p1.push_back(-1);
+                    bc.n_quartets = q;
+                    p->class_count[cid] += q;
+                    p->class_flops[cid] += flops;
+                    p->bclass.push_back(bc);
                 }
-                int64_t n = lo - k0;
-                if (cb == ck) n = std::min(n, b - b0 + 1);
-                if (n <= 0) continue;
-                p->h_seg_off.push_back(q);
-                p->h_seg_p1.push_back((int32_t)b);
-                q += n;
-                const int64_t npq = (int64_t)p->h_pairs[b].nprim * kprim[n];
-                p->n_prim_quartets += npq;
-                flops += (double)npq * tab[class_id5_of(cid)].flops_pq + (double)n * tab[class_id5_of(cid)].flops_q;
             }
-            bc.seg_hi = (int64_t)p->h_seg_p1.size();
-            if (bc.seg_hi == bc.seg_lo) continue;
-            // closing entry of the class: seg_off[seg_hi] = total quartets
-            p->h_seg_off.push_back(q);
-            p->h_seg_p1.push_back(-1);
-            bc.n_quartets = q;
-            p->class_count[cid] = q;
-            p->class_flops[cid] = flops;
-            p->bclass.push_back(bc);
         }
     }
     // ---- output ring: every quartet is written; the ring keeps the last ------
     int64_t total_eri = 0;
-    for (auto& bc : p->bclass) total_eri += bc.n_quartets * (int64_t)tab[class_id5_of(bc.cid)].n_eriq;
+    for (int c = 0; c < 256; ++c) total_eri += p->class_count[c] * (int64_t)tab[class_id5_of(c)].n_eriq;
     const int64_t per_eri = p->code_bytes > 0 ? p->code_bytes : 8;
     const double frac = (o->ring_bytes > 0 && total_eri * per_eri > o->ring_bytes)
                             ? (double)o->ring_bytes / (double)(total_eri * per_eri) : 1.0;
+    for (int c = 0; c < 256; ++c) {
+        if (!p->class_count[c]) continue;
+        int64_t r = (int64_t)std::floor(frac * (double)p->class_count[c]);
+        p->class_ring[c] = std::min<int64_t>(p->class_count[c], std::max<int64_t>(r, 1));
+    }
     for (auto& bc : p->bclass) {
-        int64_t r = (int64_t)std::floor(frac * (double)bc.n_quartets);
-        r = std::min<int64_t>(bc.n_quartets, std::max<int64_t>(r, 1));
-        bc.ring = r;
-        bc.chunk = std::min(cap, r);
+        bc.ring = p->class_ring[bc.cid];
+        bc.chunk = std::min(cap, bc.ring);
         maxchunk = std::max(maxchunk, bc.chunk);
-        p->class_ring[bc.cid] = r;
     }
     p->class_qoff[0] = 0;
     p->class_eoff[0] = 0;
@@ -575,21 +592,23 @@ extern "C" int eri_plan_quartets(const eri_plan* p, int32_t class_id, int64_t fi
         std::copy(q, q + 4 * count, out);
         return ERI_OK;
     }
-    const eri_batch_class* bc = nullptr;
-    for (auto& b : p->bclass)
-        if (b.cid == class_id) bc = &b;
-    if (!bc) return ERI_EINVAL;
-    // segment holding quartet `first`
-    int64_t sg = (int64_t)(std::upper_bound(p->h_seg_off.begin() + bc->seg_lo, p->h_seg_off.begin() + bc->seg_hi, first) -
-                           p->h_seg_off.begin()) - 1;
-    for (int64_t t = first; t < first + count; ++t) {
-        while (t >= p->h_seg_off[sg + 1]) ++sg;
-        const int32_t p1 = p->h_seg_p1[sg];
-        const int64_t p2 = bc->ket_lo + (t - p->h_seg_off[sg]);
-        const eri_shell_pair& a = p->h_pairs[p1];
-        const eri_shell_pair& b = p->h_pairs[p2];
-        int32_t* o = out + 4 * (t - first);
-        o[0] = a.sa; o[1] = a.sb; o[2] = b.sa; o[3] = b.sb;
+    for (const auto& bc : p->bclass) {
+        if (bc.cid != class_id) continue;
+        const int64_t lo = std::max(first, bc.qoff), hi = std::min(first + count, bc.qoff + bc.n_quartets);
+        if (lo >= hi) continue;
+        // segment holding entry quartet lo - qoff
+        int64_t sg = (int64_t)(std::upper_bound(p->h_seg_off.begin() + bc.seg_lo, p->h_seg_off.begin() + bc.seg_hi,
+                                                lo - bc.qoff) - p->h_seg_off.begin()) - 1;
+        for (int64_t t = lo; t < hi; ++t) {
+            const int64_t e = t - bc.qoff;
+            while (e >= p->h_seg_off[sg + 1]) ++sg;
+            const int32_t p1 = p->h_seg_p1[sg];
+            const int64_t p2 = bc.ket_lo + (e - p->h_seg_off[sg]);
+            const eri_shell_pair& a = p->h_pairs[p1];
+            const eri_shell_pair& b = p->h_pairs[p2];
+            int32_t* o = out + 4 * (t - first);
+            o[0] = a.sa; o[1] = a.sb; o[2] = b.sa; o[3] = b.sb;
+        }
     }
     return ERI_OK;
 }
@@ -642,12 +661,11 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
         a.n_items = n;
         return launch_items(ki, a, st);
     }
-    const eri_batch_class* bc = nullptr;
-    for (auto& b : p->bclass)
-        if (b.cid == c) bc = &b;
-    if (!bc) return ERI_OK;
     const auto sbeg = p->h_seg_off.begin();
-    for (int64_t q0 = 0; q0 < bc->n_quartets; q0 += bc->chunk) {
+    for (const auto& b : p->bclass) {
+      if (b.cid != c) continue;
+      const eri_batch_class* bc = &b;
+      for (int64_t q0 = 0; q0 < bc->n_quartets; q0 += bc->chunk) {
         const int64_t q1 = std::min(bc->n_quartets, q0 + bc->chunk);
         // segments overlapping [q0, q1)
         const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q0) - sbeg) - 1;
@@ -658,8 +676,9 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
         ERI_HIP_TRY(hipGetLastError());
         a.items = p->d_items;
         a.n_items = q1 - q0;
-        a.qbase = q0;
+        a.qbase = bc->qoff + q0;
         ERI_TRY(launch_items(ki, a, st));
+      }
     }
     return ERI_OK;
 }
@@ -795,11 +814,13 @@ static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, co
     // sample sizes and scratch outputs
     std::vector<int64_t> nsample(256, 0);
     int64_t max_vals = 1, max_q = 1;
+    // batched plans: the sample is the start of the class's largest entry
+    std::vector<const eri_batch_class*> sentry(256, nullptr);
+    for (const auto& b : p->bclass)
+        if (!sentry[b.cid] || b.n_quartets > sentry[b.cid]->n_quartets) sentry[b.cid] = &b;
     for (int c = 0; c < 256; ++c) {
         int64_t n = std::min(p->class_count[c], sample);
-        if (p->batched)
-            for (auto& b : p->bclass)
-                if (b.cid == c) n = std::min(n, b.chunk);
+        if (p->batched) n = sentry[c] ? std::min({n, sentry[c]->n_quartets, sentry[c]->chunk}) : 0;
         nsample[c] = n;
         max_vals = std::max(max_vals, n * (int64_t)kernel_table(p->precision)[class_id5_of(c)].n_eriq);
         max_q = std::max(max_q, n);
@@ -853,9 +874,7 @@ static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, co
         if (!p->batched) {
             a.items = p->d_items + p->class_qoff[c];
         } else {
-            const eri_batch_class* bc = nullptr;
-            for (auto& b : p->bclass)
-                if (b.cid == c) bc = &b;
+            const eri_batch_class* bc = sentry[c];
             const auto sbeg = p->h_seg_off.begin();
             const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, n) - sbeg);
             hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - bc->seg_lo)), dim3(256), 0, st, p->d_seg_off,
