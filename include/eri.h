@@ -98,7 +98,8 @@ typedef struct {
     int32_t class_n_variants[256];/* launch variants available: 0 .. n-1 */
     int32_t class_tag[256];       /* kernel of the variant in use: 0 default, 1 alternate mapping
                                      (name suffix _a), 2 half-register slots (suffix _o2),
-                                     3 two-wavefront slots (suffix _w2) */
+                                     3 two-wavefront slots (suffix _w2), 4 bra and ket exchanged
+                                     (suffix _s) */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
@@ -159,9 +160,11 @@ int eri_compute_class(eri_plan* plan, int32_t class_id, void* stream, double* ou
  * mapping at 64, 128 or 256 quartets per workgroup (one lane per quartet),
  * an alternate mapping (a slot of lanes per quartet instead of one lane, or
  * the reverse) and, for large slot-mapped classes, a kernel limited to half
- * the registers (two wavefronts per SIMD, half the LDS staging) or, where a
- * lane would hold two bra indices, a kernel that spreads them over two
- * wavefronts.  For every
+ * the registers (two wavefronts per SIMD, half the LDS staging), where a
+ * lane would hold two bra indices a kernel that spreads them over two
+ * wavefronts, and for classes whose pairs differ much in size the other
+ * bra/ket order (the plan exchanges bra and ket of the class's items when
+ * such a variant runs).  For every
  * class of the plan with more than one variant,
  * the first min(class_quartets, sample_quartets) quartets are computed with
  * each variant `trials` times on `stream` (outputs to scratch memory the call

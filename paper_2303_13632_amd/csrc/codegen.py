@@ -96,7 +96,7 @@ def kernel_name(prec, user, alt=False):
 
 # classes with one g shell and s, p, d on the others: the exponent derivatives
 # of d shells (L + 2) in the adjoint
-MAXVAR = 6   # launch variants per class (ERI_MAXVAR)
+MAXVAR = 8   # launch variants per class (ERI_MAXVAR)
 
 G_CLASSES = [c for c in itertools.product(range(5), repeat=4) if sorted(c)[-1] == 4 and sorted(c)[-2] <= 2]
 
@@ -1027,6 +1027,19 @@ def lds_chunks(cp, lds_budget):
     return (NCD + CH - 1) // CH
 
 
+def swapped_variant(cp):
+    """Classes whose two pairs differ much in size also get the other bra/ket
+    order (pairs keep their internal order).  With the large pair on the bra
+    the slot's lanes each rebuild a long bra path and the bra HRR has few ket
+    indices to spread over; with it on the ket the accumulators are many.
+    The plan swaps bra and ket of the class's items when this variant runs."""
+    if max(cp.user) > 3 or cp.Lab == cp.Lcd:
+        return None
+    if max(cp.Lab, cp.Lcd) < 5 or min(cp.Lab, cp.Lcd) > 3:
+        return None
+    return ClassPlan(*cp.user, perm=cp.perm[2:] + cp.perm[:2])
+
+
 def occupancy_variant(cp):
     """Slot-mapped classes large enough to be register-bound also get a
     kernel limited to half the registers (two wavefronts per SIMD, half the
@@ -1057,7 +1070,7 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 
 
 # kernel tags (last field of eri_kernel_info): which generated kernel a variant launches
-TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES = 0, 1, 2, 3
+TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES, TAG_SWAP = 0, 1, 2, 3, 4
 
 
 def kernel_info_init(cp, name, block=64, tag=TAG_DEFAULT):
@@ -1119,6 +1132,15 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 oname, osrc = emit_class(cp, prec, occupancy=2)
                 parts.append(osrc)
                 infos += variant_infos(cp, oname, TAG_OCC2)
+            scp = swapped_variant(cp)
+            if scp is not None:
+                sname = kernel_name(prec, cp.user) + "_s"
+                if scp.mode == "T":
+                    sname, ssrc = sname, emit_mode_T(scp, prec, sname)[1]
+                else:
+                    sname, ssrc = sname, emit_mode_W(scp, prec, sname)[1]
+                parts.append(ssrc)
+                infos += variant_infos(scp, sname, TAG_SWAP)
             if max(user) <= 3 and cp.mode == "W" and len(wave_layout(cp)[0]) == 2 and cp.Lcd >= 2:
                 wname = kernel_name(prec, cp.user) + "_w2"
                 wname, wsrc = emit_mode_W2(cp, prec, wname)

@@ -634,6 +634,8 @@ static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, h
     int nv = 0;
     while (nv < ERI_MAXVAR && var[nv].fn) ++nv;
     int best = 0;
+    // derived items are built in the default kernel's bra/ket order
+    while (nv > 1 && (var[nv - 1].perm & 3) / 2 != (var[0].perm & 3) / 2) --nv;
     if (nv > 1) {
         eri_class_args a = full;
         a.n_items = std::min<int64_t>(full.n_items, 65536);

@@ -12,7 +12,7 @@ struct eri_kernel_info {
     int32_t flops_q;     // algorithmic FLOPs per contracted quartet (HRR + quantiser)
     int32_t perm;        // computed shell k is user shell (perm >> 2k) & 3
     int32_t tag;         // generated kernel: 0 default, 1 alternate mapping, 2 half-register (2 waves/SIMD),
-                         // 3 two bra subslots on two wavefronts
+                         // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged
 };
 
 // Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by
@@ -23,6 +23,7 @@ const eri_kernel_info* eri_kernel_table(int precision);
 
 // Launch variants of every class for the autotuner: entry id5 * ERI_MAXVAR + k,
 // k = 0 the default launch of the table above; unused entries have fn == nullptr.
-// All variants of a class share its orientation (perm) and output layout.
-#define ERI_MAXVAR 6
+// Variants share the output layout; a variant may compute the class with bra
+// and ket exchanged (perm), which the plan's items must follow.
+#define ERI_MAXVAR 8
 const eri_kernel_info* eri_kernel_variants(int precision);

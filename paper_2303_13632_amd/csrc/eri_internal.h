@@ -128,6 +128,7 @@ struct eri_plan {
     int64_t class_eoff[257] = {};
     double class_flops[256] = {};
     int32_t class_var[256] = {};     // launch variant per class (0 = default; set by the autotuner)
+    bool class_items_swapped[256] = {};   // explicit plans: items hold bra and ket exchanged
     int64_t n_pairs = 0, n_prims = 0;
     std::vector<eri_shell_pair> h_pairs;   // batched plans keep the pair table on the host
     eri_shell_pair* d_pairs = nullptr;

@@ -638,6 +638,33 @@ static int launch_items(const eri_kernel_info& ki, eri_class_args& a, hipStream_
     return ERI_OK;
 }
 
+static bool kernel_swap(const eri_kernel_info& ki) { return (ki.perm & 3) >= 2; }
+
+__global__ __launch_bounds__(256) void eri_swap_items_kernel(eri_item* __restrict__ items, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const eri_item it = items[i];
+    eri_item o;
+    o.bra = it.ket;
+    o.ket = it.bra;
+    items[i] = o;
+}
+
+// Explicit plans: put the class's items in the orientation kernel `ki` computes.
+static int orient_items(eri_plan* p, int c, const eri_kernel_info& ki, hipStream_t st)
+{
+    if (p->batched || !p->class_count[c]) return ERI_OK;
+    const bool want = kernel_swap(ki) != kernel_swap(kernel_table(p->precision)[class_id5_of(c)]);
+    if (want == p->class_items_swapped[c]) return ERI_OK;
+    const int64_t n = p->class_count[c];
+    hipLaunchKernelGGL(eri_swap_items_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       p->d_items + p->class_qoff[c], n);
+    ERI_HIP_TRY(hipGetLastError());
+    p->class_items_swapped[c] = want;
+    return ERI_OK;
+}
+
 // Kernel of a class launch: the autotuner's variant, else the default.
 static const eri_kernel_info& class_kernel(const eri_plan* p, int c)
 {
@@ -657,6 +684,7 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
     eri_class_args a;
     fill_args(p, c, a, out_eri, out_codes, out_scales);
     if (!p->batched) {
+        ERI_TRY(orient_items(p, c, ki, st));
         a.items = p->d_items + p->class_qoff[c];
         a.n_items = n;
         return launch_items(ki, a, st);
@@ -672,7 +700,7 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
         const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q1) - sbeg);
         if (s1 - s0 > INT32_MAX) return ERI_EUNSUPPORTED;
         hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, st, p->d_seg_off, p->d_seg_p1,
-                           s0, bc->ket_lo, q0, q1, bc->swap ? 1 : 0, p->d_items);
+                           s0, bc->ket_lo, q0, q1, kernel_swap(ki) ? 1 : 0, p->d_items);
         ERI_HIP_TRY(hipGetLastError());
         a.items = p->d_items;
         a.n_items = q1 - q0;
@@ -871,22 +899,26 @@ static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, co
         a.ring = n;
         a.qbase = 0;
         a.n_items = n;
-        if (!p->batched) {
-            a.items = p->d_items + p->class_qoff[c];
-        } else {
-            const eri_batch_class* bc = sentry[c];
-            const auto sbeg = p->h_seg_off.begin();
-            const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, n) - sbeg);
-            hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - bc->seg_lo)), dim3(256), 0, st, p->d_seg_off,
-                               p->d_seg_p1, bc->seg_lo, bc->ket_lo, (int64_t)0, n, bc->swap ? 1 : 0, p->d_items);
-            hip(hipGetLastError());
-            a.items = p->d_items;
-        }
         double best = 0.0;
         int bestk = 0;
         for (int k = 0; k < ERI_MAXVAR && rc == ERI_OK; ++k) {
             const eri_kernel_info& ki = var[c5 * ERI_MAXVAR + k];
             if (!ki.fn) continue;
+            // the sample's items in this variant's orientation
+            if (!p->batched) {
+                rc = orient_items(p, c, ki, st);
+                a.items = p->d_items + p->class_qoff[c];
+            } else {
+                const eri_batch_class* bc = sentry[c];
+                const auto sbeg = p->h_seg_off.begin();
+                const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, n) - sbeg);
+                hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - bc->seg_lo)), dim3(256), 0, st,
+                                   p->d_seg_off, p->d_seg_p1, bc->seg_lo, bc->ket_lo, (int64_t)0, n,
+                                   kernel_swap(ki) ? 1 : 0, p->d_items);
+                hip(hipGetLastError());
+                a.items = p->d_items;
+            }
+            if (rc != ERI_OK) break;
             rc = launch_items(ki, a, st);   // warm-up
             hip(hipEventRecord(e0, st));
             for (int t = 0; t < trials && rc == ERI_OK; ++t) rc = launch_items(ki, a, st);
