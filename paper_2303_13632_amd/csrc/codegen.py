@@ -1033,9 +1033,7 @@ def swapped_variant(cp):
     the slot's lanes each rebuild a long bra path and the bra HRR has few ket
     indices to spread over; with it on the ket the accumulators are many.
     The plan swaps bra and ket of the class's items when this variant runs."""
-    if max(cp.user) > 3 or cp.Lab == cp.Lcd:
-        return None
-    if max(cp.Lab, cp.Lcd) < 5 or min(cp.Lab, cp.Lcd) > 3:
+    if max(cp.user) > 3 or cp.Lab == cp.Lcd or max(cp.Lab, cp.Lcd) < 4:
         return None
     return ClassPlan(*cp.user, perm=cp.perm[2:] + cp.perm[:2])
 
@@ -1149,6 +1147,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
                 infos.append("{(const void*)%s, 1, 128, 1, %d, %d, %d, %d, %d}"
                              % (wname, cp.n_eriq, per_pq, per_q, pk, TAG_TWO_WAVES))
+            assert len(infos) <= MAXVAR, (user, len(infos))
             for k, info in enumerate(infos):
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
         for prec, lines_ in reg.items():

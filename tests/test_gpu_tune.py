@@ -39,7 +39,7 @@ def _run(plan):
 def test_every_variant_parity(all_classes):
     shells, quartets, ref, ref_off, sizes, plan = all_classes
     nv = plan.class_n_variants
-    assert nv.min() >= 1 and nv.max() <= 6
+    assert nv.min() >= 1 and nv.max() <= 8   # ERI_MAXVAR
     assert (nv > 1).sum() >= 100, "expected alternates for many classes"
     for k in range(1, int(nv.max())):
         v = np.where(nv > k, k, 0).astype(np.int32)
