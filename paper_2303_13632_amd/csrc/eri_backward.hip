@@ -620,10 +620,25 @@ struct bwd_call {
     bool lds;
 };
 
+// Derived items of one kind in the bra/ket order of kernel `ki`.
+static int derive_items(eri_bwd_state* st, hipStream_t strm, const eri_item* uitems, int64_t m,
+                        const int32_t* origin, int pos, int kind, const int Lp[4], const eri_kernel_info& ki)
+{
+    const int kswap = (ki.perm & 3) >= 2 ? 1 : 0;
+    const unsigned g256 = (unsigned)((m + 255) / 256);
+    hipLaunchKernelGGL(eri_bwd_derive_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, origin, st->d_pairs,
+                       st->d_dmap, pos / 2, pos % 2, kind, st->null_rec, kswap, Lp[0] == Lp[1] ? 1 : 0,
+                       Lp[2] == Lp[3] ? 1 : 0, st->d_ditems);
+    ERI_HIP_TRY(hipGetLastError());
+    return ERI_OK;
+}
+
 // Launch variant of a derived class: the first pass that meets the class
-// times each variant once on up to 65536 of its items (after a warm-up
-// launch) and keeps the fastest for the rest of the plan's life.
+// times each variant once on up to 65536 of its items (derived in that
+// variant's bra/ket order, after a warm-up launch) and keeps the fastest for
+// the rest of the plan's life.
 static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, hipStream_t strm,
+                        const eri_item* uitems, const int32_t* origin, int pos, int kind, const int Lp[4],
                         const eri_kernel_info*& out)
 {
     const eri_kernel_info* var = eri_kernel_variants(0) + (int64_t)c5 * ERI_MAXVAR;
@@ -634,11 +649,12 @@ static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, h
     int nv = 0;
     while (nv < ERI_MAXVAR && var[nv].fn) ++nv;
     int best = 0;
-    // derived items are built in the default kernel's bra/ket order
-    while (nv > 1 && (var[nv - 1].perm & 3) / 2 != (var[0].perm & 3) / 2) --nv;
     if (nv > 1) {
+        // the sample is the middle of the pass (passes are ordered by
+        // primitive-quartet count, so its ends are the lightest and heaviest)
         eri_class_args a = full;
         a.n_items = std::min<int64_t>(full.n_items, 65536);
+        a.items = full.items + (full.n_items - a.n_items) / 2;
         a.ring = a.n_items;
         hipEvent_t e0, e1;
         ERI_HIP_TRY(hipEventCreate(&e0));
@@ -646,6 +662,8 @@ static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, h
         float best_ms = 0.f;
         int rc = ERI_OK;
         for (int k = 0; k < nv && rc == ERI_OK; ++k) {
+            rc = derive_items(st, strm, uitems, full.n_items, origin, pos, kind, Lp, var[k]);
+            if (rc != ERI_OK) break;
             const int64_t grid = (a.n_items + var[k].per_block - 1) / var[k].per_block;
             void* args[] = {&a};
             float ms = 0.f;
@@ -682,12 +700,6 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     derived_ls(L, pos, kind, Lp);
     const eri_kernel_info& ki = kernel_table(ERI_FP64)[class_id5(Lp[0], Lp[1], Lp[2], Lp[3])];
     if (!ki.fn) return ERI_EUNSUPPORTED;
-    const int kswap = (ki.perm & 3) >= 2 ? 1 : 0;
-    const unsigned g256 = (unsigned)((m + 255) / 256);
-    hipLaunchKernelGGL(eri_bwd_derive_kernel, dim3(g256), dim3(256), 0, strm, uitems, m, origin, st->d_pairs,
-                       st->d_dmap, pos / 2, pos % 2, kind, st->null_rec, kswap, Lp[0] == Lp[1] ? 1 : 0,
-                       Lp[2] == Lp[3] ? 1 : 0, st->d_ditems);
-    ERI_HIP_TRY(hipGetLastError());
     eri_class_args a;
     std::memset(&a, 0, sizeof(a));
     a.items = st->d_ditems;
@@ -698,7 +710,8 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     a.ring = m;
     a.qbase = 0;
     const eri_kernel_info* kv = &ki;
-    ERI_TRY(pick_variant(st, class_id5(Lp[0], Lp[1], Lp[2], Lp[3]), a, strm, kv));
+    ERI_TRY(pick_variant(st, class_id5(Lp[0], Lp[1], Lp[2], Lp[3]), a, strm, uitems, origin, pos, kind, Lp, kv));
+    ERI_TRY(derive_items(st, strm, uitems, m, origin, pos, kind, Lp, *kv));
     const int64_t grid = (m + kv->per_block - 1) / kv->per_block;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     void* args[] = {&a};
