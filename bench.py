@@ -73,9 +73,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variants (no autotuning)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices")
-    ap.add_argument("--secondary", default="mixed,int12,gradient",
+    ap.add_argument("--secondary", default="mixed,int12,fp64_out,int8,int32,gradient",
                     help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
                          "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
+                         "fp64_out / int8 / int32 (same workload with FP64 output or 8-/32-bit codes), "
                          "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy", "lattice"],
@@ -136,6 +137,13 @@ def main():
             "roofline_class": m["roofline"]["class"], "roofline_frac": m["roofline"]["frac"]}
     if "int12" in sec:
         out["secondary"]["int12_packed"] = bench_packed(args, classes, 12)
+    for name, bits in (("fp64_out", 0), ("int8", 8), ("int32", 32)):
+        if name in sec and args.precision == "fp64":
+            m = bench_classes(args, classes, "fp64", bits, max(1, args.steps // 2), 1, "")
+            out["secondary"][name] = {
+                "value": m["geris"], "unit": "GERIS", "ms_per_step": m["ms_per_step"], "tuned": m["tuned"],
+                "bits": bits, "note": "same workload, " + m["config"]["workload"].split("; ")[-1],
+                "roofline_class": m["roofline"]["class"], "roofline_frac": m["roofline"]["frac"]}
     if "gradient" in sec:
         g = bench_gradient(args, steps=1, warmup=1)
         out["secondary"]["fwd_grad"] = {k: g[k] for k in ("value", "unit", "ms_per_step", "forward_ms", "adjoint_ms",
@@ -239,7 +247,8 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
         plan.tune(sample_quartets=args.quartets_per_class, trials=2, cache=args.tune_cache or None)
         tune_s = time.time() - t0
         log("tuned in %.1fs: %d classes off the default variant" % (tune_s, int((plan.class_variant > 0).sum())))
-    _, codes, scales = plan.alloc(eri=False, codes=True)
+    # bits = 0: FP64 values are the output (no compression)
+    values, codes, scales = plan.alloc(eri=bits == 0, codes=bits > 0)
     stream = torch.cuda.current_stream()
     active = [c for c in classes if plan.class_quartets[c] > 0]
 
@@ -247,7 +256,7 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
         for i, c in enumerate(active):
             if events is not None:
                 events[i][0].record(stream)
-            plan.compute_class(c, None, codes, scales, stream=stream)
+            plan.compute_class(c, values, codes, scales, stream=stream)
             if events is not None:
                 events[i][1].record(stream)
 
@@ -291,8 +300,9 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
         with open(per_class_out, "w") as f:
             json.dump(rows, f, indent=1)
     config = {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
-                          "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, int%d per-quartet compression"
-                          % (len(active), args.quartets_per_class, precision, bits),
+                          "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, %s"
+                          % (len(active), args.quartets_per_class, precision,
+                             "int%d per-quartet compression" % bits if bits else "FP64 output, no compression"),
               "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
               "n_prim_quartets": int(plan.n_prim_quartets), "precision": precision, "bits": bits}
     res = {"geris": geris, "ms_per_step": ms_step, "config": config, "roofline": roof,

@@ -100,7 +100,8 @@ def test_fused_bit_widths(bits):
 
 
 def test_small_case_ss_ss_k3():
-    """(ss|ss), K = 3, 4096 quartets: every quartet against the oracle."""
+    """(ss|ss), K = 3, 4096 quartets: every quartet against the oracle, with
+    scale blocks of one quartet (fused) and of 64 quartets (standalone)."""
     shells, quartets = W.small_case()
     ref, _, sizes = O.eri(shells, quartets, n_threads=THREADS)
     plan, vals, codes, scales = _eri_gpu(shells, quartets, bits=16)
@@ -108,6 +109,22 @@ def test_small_case_ss_ss_k3():
     check_quartets(shells, quartets, got, ref, _blocks(sizes), sizes, THREADS)
     # one value per quartet: each code is +-(2^15-1) or 0 at block = quartet
     assert np.all(np.isin(np.abs(codes), [0, 32767]))
+    # scale blocks of 64 consecutive quartets (one wavefront's worth): the
+    # standalone compressor over the GPU values, bit-exact against the
+    # oracle's compressor, decoded values within half a step of the oracle
+    from paper_2303_13632_amd import eri
+    off = np.arange(0, len(got) + 64, 64, dtype=np.int64)
+    off[-1] = len(got)
+    dx = torch.from_numpy(got).cuda()
+    c64, s64 = eri.compress(16, dx, torch.from_numpy(off).cuda())
+    torch.cuda.synchronize()
+    oc, oe = O.compress(16, got, off)
+    assert np.array_equal(s64.cpu().numpy()[: len(off) - 1], oe)
+    assert np.array_equal(c64.cpu().numpy().astype(np.int32), oc)
+    step = np.repeat(oe, np.diff(off))
+    assert np.all(np.abs(oc * step - ref) <= step / 2 + 4 * np.spacing(np.repeat(oe / (1.0 / 32767), np.diff(off)))
+                  + 1e-12)
+    assert len(np.unique(np.abs(oc))) > 100     # G = 64 resolves the values within a block
 
 
 def test_degenerate_geometries():
@@ -162,16 +179,17 @@ def test_standalone_compress_decompress():
 
 
 def test_full_size_sampled():
-    """The full 256-class workload (65536 quartets per class, the benchmark's
-    launch configuration): 96 seeded random quartets per class checked one by
-    one against the oracle, codes of those quartets against the oracle's
-    compressor."""
+    """The full 256-class workload (65536 quartets per class) in the
+    benchmark's launch configuration (autotuned variants): 96 seeded random
+    quartets per class checked one by one against the oracle, codes of those
+    quartets against the oracle's compressor."""
     from paper_2303_13632_amd import eri
     qpc = 65536
     parts = [W.class_case(cid, n_quartets=qpc) for cid in range(256)]
     shells, quartets = W.merge(parts)
     del parts
     plan = eri.Plan(shells, quartets, precision="fp64", bits=16)
+    plan.tune(sample_quartets=qpc, trials=2)
     e, c, s = plan.alloc(eri=True, codes=True)
     plan.compute(e, c, s)
     torch.cuda.synchronize()
