@@ -234,8 +234,10 @@ int eri_backward(eri_plan* plan, void* stream, const double* dl_deri, const doub
  * ceil(size_b / floor(512/n)); code k of a block sits in word k / per at
  * bits (k mod per) * n .. + n - 1 (little-endian across the word's eight
  * 64-bit lanes), as its n low two's-complement bits; unused bits are zero.
- * block_off, word_off: device int64, n_blocks + 1 entries; packed: device,
- * n_words * 64 bytes.  ERI_EUNSUPPORTED for n outside [2, 32]. */
+ * block_off, word_off: device int64, n_blocks + 1 entries, with
+ * block_off[0] = word_off[0] = 0 and word_off[n_blocks] = n_words (the
+ * kernel trusts them: other offsets read outside the arrays); packed:
+ * device, n_words * 64 bytes.  ERI_EUNSUPPORTED for n outside [2, 32]. */
 int eri_pack(int32_t bits, const void* codes, int64_t n_blocks, const int64_t* block_off,
              const int64_t* word_off, int64_t n_words, void* packed, void* stream);
 

@@ -1051,34 +1051,58 @@ extern "C" int eri_decompress(int32_t bits, const void* codes, const double* sca
 
 // ---------------------------------------------------------------------------
 // Packed code stream: 512-bit words of floor(512 / n) n-bit codes, each block
-// (quartet) starting on a word.  One thread per word.
+// (quartet) starting on a word.  A wavefront packs a tile of ERI_PACK_TILE
+// consecutive words; lane l builds 64-bit lane (l & 7) of words
+// w0 + (l >> 3) + 8 i, so each store instruction writes eight whole
+// consecutive words (512 contiguous bytes) and the lanes read consecutive
+// runs of codes.  The block of the tile's first word is found by a binary
+// search over word_off, later blocks by stepping forward; the current
+// block's bounds stay in registers.
 // ---------------------------------------------------------------------------
+constexpr int64_t ERI_PACK_TILE = 2048;
+
 template <typename CT>
 __global__ __launch_bounds__(256) void eri_pack_kernel(const CT* __restrict__ codes, const int64_t* __restrict__ off,
                                                        const int64_t* __restrict__ woff, int64_t n_blocks,
                                                        int64_t n_words, int bits, uint64_t* __restrict__ packed)
 {
-    const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (w >= n_words) return;
-    // block owning word w: last b with woff[b] <= w
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = wave * ERI_PACK_TILE;
+    if (w0 >= n_words) return;   // uniform over the wavefront
+    const int64_t w1 = w0 + ERI_PACK_TILE < n_words ? w0 + ERI_PACK_TILE : n_words;
+    // last block b with woff[b] <= w0 (blocks of zero codes own no word)
     int64_t lo = 0, hi = n_blocks;
     while (hi - lo > 1) {
         const int64_t mid = (lo + hi) >> 1;
-        if (woff[mid] <= w) lo = mid; else hi = mid;
+        if (woff[mid] <= w0) lo = mid; else hi = mid;
     }
+    int64_t b = lo;
+    const int q = lane & 7;
     const int per = 512 / bits;
-    const int64_t first = off[lo] + (w - woff[lo]) * per;
-    const int64_t end = off[lo + 1];
-    const uint64_t mask = bits == 64 ? ~0ull : ((1ull << bits) - 1ull);
-    uint64_t out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < per && first + k < end; ++k) {
-        const uint64_t v = (uint64_t)(int64_t)codes[first + k] & mask;
-        const int bit = k * bits;
-        const int q = bit >> 6, r = bit & 63;
-        out[q] |= v << r;
-        if (r + bits > 64) out[q + 1] |= v >> (64 - r);
+    const uint64_t mask = (1ull << bits) - 1ull;   // bits <= 32
+    // codes overlapping bits [64 q, 64 q + 64) of a word
+    const int k0 = (64 * q) / bits;
+    const int k1 = min(per - 1, (64 * q + 63) / bits);
+    // the current block's first word, the next block's first word, its code range
+    int64_t wb = woff[b], wn = b + 1 < n_blocks ? woff[b + 1] : INT64_MAX, ob = off[b], oe = off[b + 1];
+    for (int64_t w = w0 + (lane >> 3); w < w1; w += 8) {
+        if (w >= wn) {
+            while (b + 1 < n_blocks && woff[b + 1] <= w) ++b;
+            wb = woff[b];
+            wn = b + 1 < n_blocks ? woff[b + 1] : INT64_MAX;
+            ob = off[b];
+            oe = off[b + 1];
+        }
+        const int64_t first = ob + (w - wb) * per;
+        uint64_t out = 0;
+        for (int k = k0; k <= k1 && first + k < oe; ++k) {
+            const uint64_t v = (uint64_t)(int64_t)codes[first + k] & mask;
+            const int sh = k * bits - 64 * q;   // in (-bits, 64)
+            out |= sh >= 0 ? (v << sh) : (v >> -sh);
+        }
+        packed[8 * w + q] = out;
     }
-    for (int q = 0; q < 8; ++q) packed[8 * w + q] = out[q];
 }
 
 // Decode: one thread per code; sign-extends the n-bit field.
@@ -1116,7 +1140,8 @@ extern "C" int eri_pack(int32_t bits, const void* codes, int64_t n_blocks, const
     if (n_blocks < 0 || n_words < 0 || (n_words > 0 && (!codes || !block_off || !word_off || !packed)))
         return ERI_EINVAL;
     if (n_words == 0 || n_blocks == 0) return ERI_OK;
-    const int64_t grid = (n_words + 255) / 256;
+    const int64_t waves = (n_words + ERI_PACK_TILE - 1) / ERI_PACK_TILE;
+    const int64_t grid = (waves + 3) / 4;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     if (bits <= 8)

@@ -12,7 +12,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("bits", [12, 10, 16, 20])
+@pytest.mark.parametrize("bits", [12, 10, 16, 20, 3, 7, 32])
 def test_packed_stream(bits):
     from paper_2303_13632_amd import eri
     parts = [W.class_case(cid, n_quartets=9, seed=W.SEED_BASE + 81) for cid in (0, 21, 85, 170, 238, 255)]
