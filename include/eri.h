@@ -99,7 +99,8 @@ typedef struct {
     int32_t class_tag[256];       /* kernel of the variant in use: 0 default, 1 alternate mapping
                                      (name suffix _a), 2 half-register slots (suffix _o2),
                                      3 two-wavefront slots (suffix _w2), 4 bra and ket exchanged
-                                     (suffix _s) */
+                                     (suffix _s), 5 two-wavefront slots at half the registers
+                                     (suffix _w2o2) */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on

@@ -767,7 +767,7 @@ def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     return name, em.text()
 
 
-def emit_mode_W2(cp, prec, name, lds_budget=32768):
+def emit_mode_W2(cp, prec, name, lds_budget=32768, waves=1):
     """Two-subslot classes (|e| <= 6, 84 bra indices) on two wavefronts: wave
     w holds the bra indices of parity w, one per lane, so a lane carries one
     set of accumulators instead of two.  The ket VRR's coupling term comes
@@ -821,7 +821,11 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768):
         NX = max(NX, k)
     NF = cp.Ltot + 1 + 17
     NSU = max(NTE * CH, NF * 64 + 2 * NX * 64)
-    em("__global__ __launch_bounds__(128) void %s(eri_class_args A)" % name)
+    if waves > 1:
+        # `waves` workgroups per CU's SIMD pair: the register budget halves
+        em("__global__ __launch_bounds__(128, %d) void %s(eri_class_args A)" % (waves, name))
+    else:
+        em("__global__ __launch_bounds__(128) void %s(eri_class_args A)" % name)
     em.block("")
     em("__shared__ double s_u[%d];" % NSU)
     em("double (*s_x)[%d][64] = reinterpret_cast<double (*)[%d][64]>(s_u + %d);   // [wave][value][lane]"
@@ -1069,6 +1073,19 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 
 # kernel tags (last field of eri_kernel_info): which generated kernel a variant launches
 TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES, TAG_SWAP = 0, 1, 2, 3, 4
+TAG_TWO_WAVES_OCC2 = 5
+
+
+def two_wave_form(cp):
+    """Slot-mapped plans with two bra indices per lane (an f-f bra) also get
+    the two-wavefront kernel."""
+    return cp.mode == "W" and len(wave_layout(cp)[0]) == 2 and cp.Lcd >= 2
+
+
+def w2_info(cp, name, tag):
+    per_pq, per_q = cp.flops()
+    pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
+    return "{(const void*)%s, 1, 128, 1, %d, %d, %d, %d, %d}" % (name, cp.n_eriq, per_pq, per_q, pk, tag)
 
 
 def kernel_info_init(cp, name, block=64, tag=TAG_DEFAULT):
@@ -1139,14 +1156,16 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                     sname, ssrc = sname, emit_mode_W(scp, prec, sname)[1]
                 parts.append(ssrc)
                 infos += variant_infos(scp, sname, TAG_SWAP)
-            if max(user) <= 3 and cp.mode == "W" and len(wave_layout(cp)[0]) == 2 and cp.Lcd >= 2:
+            if max(user) <= 3 and two_wave_form(cp):
                 wname = kernel_name(prec, cp.user) + "_w2"
-                wname, wsrc = emit_mode_W2(cp, prec, wname)
-                parts.append(wsrc)
-                per_pq, per_q = cp.flops()
-                pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
-                infos.append("{(const void*)%s, 1, 128, 1, %d, %d, %d, %d, %d}"
-                             % (wname, cp.n_eriq, per_pq, per_q, pk, TAG_TWO_WAVES))
+                parts.append(emit_mode_W2(cp, prec, wname)[1])
+                infos.append(w2_info(cp, wname, TAG_TWO_WAVES))
+                if cp.Lcd <= 4:
+                    # small ket: the half-register form spills a few hundred bytes per lane
+                    # and runs two workgroups per SIMD pair ([ff|fp]: 7.5 -> 5.0 ms); with a
+                    # larger ket, or with bra and ket exchanged, it never beat the others
+                    parts.append(emit_mode_W2(cp, prec, wname + "o2", waves=2)[1])
+                    infos.append(w2_info(cp, wname + "o2", TAG_TWO_WAVES_OCC2))
             assert len(infos) <= MAXVAR, (user, len(infos))
             for k, info in enumerate(infos):
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))

@@ -12,7 +12,8 @@ struct eri_kernel_info {
     int32_t flops_q;     // algorithmic FLOPs per contracted quartet (HRR + quantiser)
     int32_t perm;        // computed shell k is user shell (perm >> 2k) & 3
     int32_t tag;         // generated kernel: 0 default, 1 alternate mapping, 2 half-register (2 waves/SIMD),
-                         // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged
+                         // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged, 5 two wavefronts
+                         // at half the registers
 };
 
 // Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by
