@@ -20,36 +20,43 @@ THREADS = min(16, os.cpu_count() or 1)
 
 
 def test_mixed_per_class_error():
+    """Every launch variant of every class (the autotuner may pick any): per
+    class, the largest error over the variants is reported; each variant's
+    fused codes equal the compressor applied to its own doubles."""
     from paper_2303_13632_amd import eri
     parts = [W.class_case(cid, n_quartets=N_PER_CLASS, seed=W.SEED_BASE + 71) for cid in range(256)]
     shells, quartets = W.merge(parts)
     ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
     plan = eri.Plan(shells, quartets, precision="mixed", bits=16)
-    e, c, s = plan.alloc(eri=True, codes=True)
-    plan.compute(e, c, s)
-    torch.cuda.synchronize()
-    vals = e.cpu().numpy()[: plan.n_eri]
-    got = plan.to_user(vals)
-    assert np.all(np.isfinite(got))
-    rows = []
-    for cid in range(256):
-        lo = ref_off[cid * N_PER_CLASS]
-        hi = ref_off[(cid + 1) * N_PER_CLASS - 1] + sizes[(cid + 1) * N_PER_CLASS - 1]
-        err = np.abs(got[lo:hi] - ref[lo:hi])
-        rows.append((float(err.max()), float(np.abs(ref[lo:hi]).max()), cid))
-    rows.sort(reverse=True)
-    print("FP32-mixed max |error| per class (worst 12): " +
-          ", ".join("c%03d %.2e (max|x| %.2e)" % (c_, e_, m_) for e_, m_, c_ in rows[:12]))
-    print("classes within 1e-7 Ha: %d of 256" % sum(1 for r in rows if r[0] <= 1e-7))
-    assert rows[0][0] <= 1e-2
-    # compression of the mixed values is exact (FP64 quantiser on the same doubles)
-    off = []
-    for cid in range(256):
-        n = int(plan.class_quartets[cid])
-        if n:
-            m = int((plan.class_eri_off[cid + 1] - plan.class_eri_off[cid]) // n)
-            off.append(plan.class_eri_off[cid] + m * np.arange(n))
-    off = np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
-    oc, oe = O.compress(16, vals, off)
-    assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32))
-    assert np.array_equal(oe, s.cpu().numpy()[: plan.n_quartets])
+    nv = plan.class_n_variants
+    worst = np.zeros(256)
+    for k in range(int(nv.max())):
+        v = np.where(nv > k, k, 0).astype(np.int32)
+        plan.set_variants(v)
+        e, c, s = plan.alloc(eri=True, codes=True)
+        plan.compute(e, c, s)
+        torch.cuda.synchronize()
+        vals = e.cpu().numpy()[: plan.n_eri]
+        got = plan.to_user(vals)
+        assert np.all(np.isfinite(got)), k
+        for cid in np.nonzero(v == k)[0]:
+            lo = ref_off[cid * N_PER_CLASS]
+            hi = ref_off[(cid + 1) * N_PER_CLASS - 1] + sizes[(cid + 1) * N_PER_CLASS - 1]
+            worst[cid] = max(worst[cid], float(np.abs(got[lo:hi] - ref[lo:hi]).max()))
+        # compression of the mixed values is exact (FP64 quantiser on the same doubles)
+        off = []
+        for cid in range(256):
+            n = int(plan.class_quartets[cid])
+            if n:
+                m = int((plan.class_eri_off[cid + 1] - plan.class_eri_off[cid]) // n)
+                off.append(plan.class_eri_off[cid] + m * np.arange(n))
+        off = np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
+        oc, oe = O.compress(16, vals, off)
+        assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32)), k
+        assert np.array_equal(oe, s.cpu().numpy()[: plan.n_quartets]), k
+    plan.set_variants(np.zeros(256, np.int32))
+    order = np.argsort(-worst)
+    print("FP32-mixed max |error| per class over its variants (worst 12): " +
+          ", ".join("c%03d %.2e" % (c_, worst[c_]) for c_ in order[:12]))
+    print("classes within 1e-7 Ha: %d of 256; median %.1e Ha" % (int((worst <= 1e-7).sum()), float(np.median(worst))))
+    assert worst.max() <= 1e-2
