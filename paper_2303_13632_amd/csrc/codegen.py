@@ -759,8 +759,11 @@ def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     em("const double eps = m * A.cn;")
     em("const double inv = eri_inverse_scale(eps);")
     em("if (active && ls == 0 && A.out_scales) A.out_scales[oslot] = eps;")
+    # with a single chunk its ket-HRR staging is still in LDS: only the bra
+    # HRR is repeated (with several chunks, re-ordering them measured slower)
     for ch in range(NCH):
-        ket_hrr_chunk(ch)
+        if NCH > 1:
+            ket_hrr_chunk(ch)
         bra_hrr_chunk(ch, 2)
     em.end()
     em.end()
@@ -1003,8 +1006,11 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768, waves=1):
     em("const double eps = m * A.cn;")
     em("const double inv = eri_inverse_scale(eps);")
     em("if (active && tid == 0 && A.out_scales) A.out_scales[oslot] = eps;")
+    # with a single chunk its ket-HRR staging is still in LDS: only the bra
+    # HRR is repeated (with several chunks, re-ordering them measured slower)
     for ch in range(NCH):
-        ket_hrr_chunk(ch)
+        if NCH > 1:
+            ket_hrr_chunk(ch)
         bra_hrr_chunk(ch, 2)
     em.end()
     em.end()

@@ -213,7 +213,7 @@ class Plan:
     def kernel_name(self, cid):
         """Name of the kernel a class launch uses (variant included)."""
         prec = "mixed" if self.precision == "mixed" else "fp64"
-        return "eri_%s_c%03d%s" % (prec, cid, {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2"}[int(self.class_tag[cid])])
+        return "eri_%s_c%03d%s" % (prec, cid, KERNEL_TAG_SUFFIX[int(self.class_tag[cid])])
 
     def layout(self):
         """(pos, eri_off) per user quartet (plan position, first ERI)."""
@@ -327,6 +327,10 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# Name suffix of the generated kernel of each variant tag (eri_plan_info.class_tag)
+KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2"}
 
 
 def _ncart(L):

@@ -72,3 +72,24 @@ def test_null_arguments():
     assert lib.eri_plan_create(ctypes.byref(h), -1, np.zeros(1, np.int32), np.zeros(1, np.int32),
                                np.zeros(3), np.zeros(2, np.int64), np.zeros(1), np.zeros(1),
                                np.zeros(4, np.int32), 0, ctypes.byref(eri.PlanOpts(0, 16, 0, 0))) == eri.ERI_EINVAL
+
+
+def test_kernel_tag_suffixes_match_generator():
+    """The binding's kernel-name suffix per variant tag is the one the
+    generator gives the kernels it registers under that tag."""
+    import importlib.util
+    import os
+    from paper_2303_13632_amd import eri
+    path = os.path.join(os.path.dirname(eri.__file__), "csrc", "codegen.py")
+    spec = importlib.util.spec_from_file_location("eri_codegen", path)
+    G = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    tags = {v: k for k, v in vars(G).items() if k.startswith("TAG_") and isinstance(v, int)}
+    assert set(tags) == set(eri.KERNEL_TAG_SUFFIX)
+    # generated names: default, half-register, two-wavefront forms of [ff|fp]
+    cp = G.ClassPlan(3, 3, 3, 1)
+    name = G.kernel_name("fp64", cp.user)
+    assert G.emit_class(cp, "fp64", occupancy=2)[0] == name + eri.KERNEL_TAG_SUFFIX[G.TAG_OCC2]
+    assert G.emit_class(G.ClassPlan(3, 3, 3, 1), "fp64", alt=True)[0] == \
+        G.kernel_name("fp64", cp.user, True)
+    assert G.kernel_name("fp64", cp.user, True) == name + eri.KERNEL_TAG_SUFFIX[G.TAG_ALT]
