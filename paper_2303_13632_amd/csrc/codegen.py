@@ -505,7 +505,7 @@ def wave_layout(cp):
     return subs, ep
 
 
-def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
+def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     real = REALS[prec]
     mixed = prec == "mixed"
     em = Emitter()
@@ -513,6 +513,11 @@ def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     subs, EP = wave_layout(cp)
     S = len(subs)
     NSLOT = 64 // EP
+    if lds_budget is None:
+        # 32 KB of HRR staging, or 40 KB where that makes it a single chunk,
+        # which the codes pass then reuses (for bras of L >= 3 such kernels are
+        # register-bound at four workgroups per CU: the LDS costs no occupancy)
+        lds_budget = 40960 if NSLOT <= 3 and lds_chunks(cp, 32768) > 1 and lds_chunks(cp, 40960) == 1 else 32768
     E_T = cp.E_T
     tgt_index = {e: k for k, e in enumerate(E_T)}
     NTE = len(E_T)
@@ -770,7 +775,7 @@ def emit_mode_W(cp, prec, name, lds_budget=32768, waves=1):
     return name, em.text()
 
 
-def emit_mode_W2(cp, prec, name, lds_budget=32768, waves=1):
+def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
     """Two-subslot classes (|e| <= 6, 84 bra indices) on two wavefronts: wave
     w holds the bra indices of parity w, one per lane, so a lane carries one
     set of accumulators instead of two.  The ket VRR's coupling term comes
@@ -790,6 +795,10 @@ def emit_mode_W2(cp, prec, name, lds_budget=32768, waves=1):
     NTE = len(E_T)
     ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
     NCD = len(cc) * len(cd)
+    if lds_budget is None:
+        # the whole ket-HRR staging in one chunk when it fits 64 KB ([ff|ff]:
+        # 59 KB, two workgroups per CU still fit), else 32 KB chunks
+        lds_budget = 65536 if NCD * NTE * 8 <= 65536 else 32768
     CH = min(NCD, max(1, lds_budget // (8 * NTE)))
     NCH = (NCD + CH - 1) // CH
     Lcd = cp.Lcd
@@ -1052,7 +1061,7 @@ def occupancy_variant(cp):
     """Slot-mapped classes large enough to be register-bound also get a
     kernel limited to half the registers (two wavefronts per SIMD, half the
     LDS staging).  Not for classes with two bra indices per lane whose
-    staging would need more chunks than the default: an [ff|ff] kernel
+    staging would need more chunks than a 32 KB one: an [ff|ff] kernel
     staged in three or more chunks returned wrong values on the GPU while the
     same source run on the CPU gave the right ones, a failure not understood."""
     if cp.mode != "W" or cp.Ltot < 6:
