@@ -468,6 +468,29 @@ def emit_slot(em, idx):
     em("const int64_t oslot = gq < A.ring ? gq : gq % A.ring;")
 
 
+def emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, slow_expr):
+    """Second pass of a slot kernel: quantise and store.  The container width
+    and whether any reciprocal 1/eps of the workgroup overflows are uniform
+    over the workgroup, so they are decided once: the common case stores
+    through a typed pointer with the multiply-by-reciprocal quantiser; the
+    general case (eps so small that 1/eps overflows: codes from x / eps) keeps
+    the generic store."""
+    em("const int slow = %s;" % slow_expr)
+    for i, (ct, nb) in enumerate((("int16_t", 2), ("int8_t", 1), ("int32_t", 4))):
+        em.block("%s (!slow && A.code_bytes == %d)" % ("if" if i == 0 else "else if", nb))
+        for ch in range(NCH):
+            if NCH > 1:
+                ket_hrr_chunk(ch)
+            bra_hrr_chunk(ch, 2, ct)
+        em.end()
+    em.block("else")
+    for ch in range(NCH):
+        if NCH > 1:
+            ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 2)
+    em.end()
+
+
 def emit_store_T(em, cp, outs):
     n = cp.n_eriq
     emit_slot(em, "t")
@@ -719,7 +742,7 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             em.end()
         em("__syncthreads();")
 
-    def bra_hrr_chunk(ch, pass_no):
+    def bra_hrr_chunk(ch, pass_no, ctype=None):
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
         em.block("for (int j = ls; j < %d; j += %d)" % (n, EP))
@@ -746,8 +769,11 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             if pass_no == 1:
                 em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
-            else:
+            elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
+            else:
+                em("reinterpret_cast<%s*>(A.out_codes)[obase + %s] = (%s)eri_quantize_mul(x%d, inv, A.qmax);"
+                   % (ctype, ix, ctype, k))
         em.end()
         em.end()
 
@@ -766,10 +792,7 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     em("if (active && ls == 0 && A.out_scales) A.out_scales[oslot] = eps;")
     # with a single chunk its ket-HRR staging is still in LDS: only the bra
     # HRR is repeated (with several chunks, re-ordering them measured slower)
-    for ch in range(NCH):
-        if NCH > 1:
-            ket_hrr_chunk(ch)
-        bra_hrr_chunk(ch, 2)
+    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__syncthreads_or(__builtin_isinf(inv) ? 1 : 0)")
     em.end()
     em.end()
     return name, em.text()
@@ -971,7 +994,7 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
         em.end()
         em("__syncthreads();")
 
-    def bra_hrr_chunk(ch, pass_no):
+    def bra_hrr_chunk(ch, pass_no, ctype=None):
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
         em.block("for (int j = tid; j < %d; j += 128)" % n)
@@ -997,8 +1020,11 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
             if pass_no == 1:
                 em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
-            else:
+            elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
+            else:
+                em("reinterpret_cast<%s*>(A.out_codes)[obase + %s] = (%s)eri_quantize_mul(x%d, inv, A.qmax);"
+                   % (ctype, ix, ctype, k))
         em.end()
         em.end()
 
@@ -1017,10 +1043,7 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
     em("if (active && tid == 0 && A.out_scales) A.out_scales[oslot] = eps;")
     # with a single chunk its ket-HRR staging is still in LDS: only the bra
     # HRR is repeated (with several chunks, re-ordering them measured slower)
-    for ch in range(NCH):
-        if NCH > 1:
-            ket_hrr_chunk(ch)
-        bra_hrr_chunk(ch, 2)
+    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__builtin_isinf(inv) ? 1 : 0")
     em.end()
     em.end()
     return name, em.text()

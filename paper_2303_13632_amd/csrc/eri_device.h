@@ -95,6 +95,14 @@ ERI_DEV int eri_quantize(double x, double eps, double inv, double qmax)
     return (int)y;
 }
 
+// eq. 10 when 1/eps is finite: round half away from zero, clamp to
+// +-qmax (eps = 0 comes with inv = 0, hence code 0, as eri_quantize gives)
+ERI_DEV int eri_quantize_mul(double x, double inv, double qmax)
+{
+    const double y = round(x * inv);
+    return (int)fmin(fmax(y, -qmax), qmax);
+}
+
 ERI_DEV void eri_store_code(void* codes, int64_t idx, int bytes, int q)
 {
     if (bytes == 2)
