@@ -742,7 +742,7 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             em.end()
         em("__syncthreads();")
 
-    def bra_hrr_chunk(ch, pass_no, ctype=None):
+    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True):
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
         em.block("for (int j = ls; j < %d; j += %d)" % (n, EP))
@@ -767,7 +767,10 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
             ix = "%s + kx" % bra
             if pass_no == 1:
-                em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                if store_values is None:
+                    em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                elif store_values:
+                    em("A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
             elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
@@ -778,9 +781,20 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
         em.end()
 
     em("double bmax = 0.0;")
-    for ch in range(NCH):
-        ket_hrr_chunk(ch)
-        bra_hrr_chunk(ch, 1)
+    # first pass: b_max, and the FP64 values when requested, decided once (the
+    # output pointer is uniform) except in the half-register kernels, where
+    # the duplicated code measured slower than a branch per value
+    if waves == 1:
+        for store in (True, False):
+            em.block("if (A.out_eri)" if store else "else")
+            for ch in range(NCH):
+                ket_hrr_chunk(ch)
+                bra_hrr_chunk(ch, 1, store_values=store)
+            em.end()
+    else:
+        for ch in range(NCH):
+            ket_hrr_chunk(ch)
+            bra_hrr_chunk(ch, 1, store_values=None)
     em("__syncthreads();")
     em("s_red[lane] = bmax;")
     em("__syncthreads();")
@@ -994,7 +1008,7 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
         em.end()
         em("__syncthreads();")
 
-    def bra_hrr_chunk(ch, pass_no, ctype=None):
+    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True):
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
         em.block("for (int j = tid; j < %d; j += 128)" % n)
@@ -1018,7 +1032,10 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
             ix = "%s + kx" % bra
             if pass_no == 1:
-                em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                if store_values is None:
+                    em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
+                elif store_values:
+                    em("A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
             elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
@@ -1029,9 +1046,14 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
         em.end()
 
     em("double bmax = 0.0;")
-    for ch in range(NCH):
-        ket_hrr_chunk(ch)
-        bra_hrr_chunk(ch, 1)
+    # first pass: b_max, and the FP64 values when requested (decided once:
+    # the output pointer is uniform)
+    for store in (True, False):
+        em.block("if (A.out_eri)" if store else "else")
+        for ch in range(NCH):
+            ket_hrr_chunk(ch)
+            bra_hrr_chunk(ch, 1, store_values=store)
+        em.end()
     em("__syncthreads();")
     em("s_red[tid] = bmax;")
     em("__syncthreads();")
