@@ -25,7 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GERIS (1e9 ERIs/s) incl. int16 compression, FP64 vs FP32-mixed, + fwd+grad"
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector FP64 / FP32 (published)
+# MI355X vector peaks: FP64 78.6 TFLOP/s (published).  The published FP32 vector peak, 157.3 TFLOP/s,
+# counts packed FP32 instructions, which this build does not emit; unpacked FP32 issues at the FP64
+# rate, so FP32-mixed kernels are held to 78.6 as well.
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 78.6}
 
 
 def log(*a):
@@ -87,7 +90,7 @@ def main():
     ap.add_argument("--schwarz", type=float, default=1e-10)
     ap.add_argument("--fd-sample", type=int, default=0,
                     help="gradient workload: check this many coordinates and as many exponents by central "
-                         "differences (h = 1e-4) of the GPU energy")
+                         "differences (h = 1e-4) of the GPU energy on the same quartet set")
     ap.add_argument("--ring-gb", type=float, default=48.0)
     args = ap.parse_args()
 
@@ -132,8 +135,11 @@ def main():
         m = bench_classes(args, classes, "mixed", args.bits, max(1, args.steps // 2), 1, "")
         out["secondary"]["fp32_mixed"] = {
             "value": m["geris"], "unit": "GERIS", "ms_per_step": m["ms_per_step"], "tuned": m["tuned"],
-            "note": "same workload; FP32 VRR/HRR, FP64 Boys/prefactor/accumulation; the 1e-7 Ha accuracy target "
-                    "is not met by every class (reported by tests/test_gpu_mixed.py)",
+            "note": "same workload; FP32 VRR/HRR with FP64 Boys/prefactor/accumulation for the %d classes "
+                    "whose FP32 error was measured within 1e-8 Ha, FP64 kernels for the other %d (FP32 "
+                    "recurrences miss the 1e-7 Ha target there); roofline against the unpacked-FP32 = FP64 "
+                    "rate of 78.6 TFLOP/s" % (m["n_fp32"], 256 - m["n_fp32"]),
+            "n_fp32_classes": m["n_fp32"],
             "roofline_class": m["roofline"]["class"], "roofline_frac": m["roofline"]["frac"]}
     if "int12" in sec:
         out["secondary"]["int12_packed"] = bench_packed(args, classes, 12)
@@ -306,6 +312,7 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
               "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
               "n_prim_quartets": int(plan.n_prim_quartets), "precision": precision, "bits": bits}
     res = {"geris": geris, "ms_per_step": ms_step, "config": config, "roofline": roof,
+           "n_fp32": int(plan.class_fp32[active].sum()),
            "whole_step_tflops": total_flops / (ms_step / 1e3) / 1e12, "active": active,
            "tuned": not args.no_tune, "tune_s": tune_s}
     del codes, scales
@@ -526,45 +533,46 @@ def bench_gradient(args, steps=None, warmup=None):
         "grad_exps_norm": float(ge.norm().item()),
     }
     if args.fd_sample > 0:
-        out["fd_check"] = fd_check(sh, D, gc.cpu().numpy(), ge.cpu().numpy(), args)
+        out["fd_check"] = fd_check(plan, D, gc.cpu().numpy(), ge.cpu().numpy(), args)
     return out
 
 
-def fd_check(sh, D, gc, ge, args, h=1e-4):
-    """Central differences of the GPU energy (new screened plan per point,
-    energy-only eri_backward) for a seeded sample of coordinates and
-    exponents; errors relative to max(|g_FD|, 1e-8 max|g|)."""
-    import torch
-    from paper_2303_13632_amd import eri
+def fd_check(plan, D, gc, ge, args, h=1e-4):
+    """Central differences of the GPU energy E = sum D D (ab|cd) for a seeded
+    sample of coordinates and exponents, on the plan's own quartet set (the
+    geometry is changed in place with eri_plan_set_geometry, so the screened
+    set stays fixed) with the energy summed in a fixed order (energy-only
+    eri_backward).  Errors relative to max(|g_FD|, 1e-8 max|g|); the plain
+    difference at h and a Richardson extrapolation from h and 2h."""
     rng = np.random.default_rng(20230323 + 5)
     gmax = max(np.abs(gc).max(), np.abs(ge).max())
+    xyz0 = np.array(plan.shells["xyz"], dtype=np.float64).reshape(-1)
+    exps0 = np.array(plan.shells["exps"], dtype=np.float64)
 
-    def energy(s2):
-        p2 = eri.Plan(s2, None, precision="fp64", bits=0, schwarz=args.schwarz)
-        _, _, en = p2.backward(density=D, energy_only=True)
+    def energy(key, idx, d):
+        x, e = xyz0.copy(), exps0.copy()
+        (x if key == "xyz" else e)[idx] += d
+        plan.set_geometry(xyz=x, exps=e)
+        _, _, en = plan.backward(density=D, energy_only=True)
         return float(en.item())
 
     def central(key, idx, step):
-        vals = []
-        for d in (step, -step):
-            s2 = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in sh.items()}
-            s2[key].reshape(-1)[idx] += d
-            vals.append(energy(s2))
-        return (vals[0] - vals[1]) / (2 * step)
+        return (energy(key, idx, step) - energy(key, idx, -step)) / (2 * step)
 
     rows = []
-    for key, n_all, g in (("xyz", 3 * len(sh["L"]), gc.reshape(-1)), ("exps", len(sh["exps"]), ge)):
+    for key, n_all, g in (("xyz", len(xyz0), gc.reshape(-1)), ("exps", len(exps0), ge)):
         for idx in rng.choice(n_all, size=min(args.fd_sample, n_all), replace=False):
             fd = central(key, idx, h)
-            # Richardson extrapolation from steps 10h and 5h: O(h^4) truncation
-            # with ten times less rounding noise than the plain h difference
-            rich = (4 * central(key, idx, 5 * h) - central(key, idx, 10 * h)) / 3
+            rich = (4 * fd - central(key, idx, 2 * h)) / 3
+            floor = 1e-8 * gmax
             rows.append({"param": key, "index": int(idx), "analytic": float(g[idx]), "fd": fd, "fd_richardson": rich,
-                         "rel": abs(fd - g[idx]) / max(abs(fd), 1e-8 * gmax),
-                         "rel_richardson": abs(rich - g[idx]) / max(abs(rich), 1e-8 * gmax)})
+                         "rel": abs(fd - g[idx]) / max(abs(fd), floor),
+                         "rel_richardson": abs(rich - g[idx]) / max(abs(rich), floor)})
         log("fd %s done" % key)
+    plan.set_geometry(xyz=xyz0, exps=exps0)
     return {"h": h, "n": len(rows), "max_rel": max(r["rel"] for r in rows),
             "max_rel_richardson": max(r["rel_richardson"] for r in rows),
+            "n_rel_above_1e-6": int(sum(r["rel"] > 1e-6 for r in rows)),
             "max_abs_over_gmax": max(abs(r["fd"] - r["analytic"]) for r in rows) / gmax,
             "worst": max(rows, key=lambda r: r["rel"])}
 

@@ -59,7 +59,9 @@ extern "C" {
 #define ERI_MAX_K 16
 
 #define ERI_FP64 0             /* recurrences in FP64 */
-#define ERI_FP32_MIXED 1       /* VRR/HRR in FP32; Boys, prefactors, contraction in FP64 */
+#define ERI_FP32_MIXED 1       /* VRR/HRR in FP32; Boys, prefactors, contraction in FP64 -- for
+                                  the classes whose FP32 recurrences meet 1e-7 Ha with a tenfold
+                                  margin (eri_plan_info.class_fp32); FP64 kernels for the rest */
 
 typedef struct eri_plan eri_plan;
 
@@ -72,7 +74,14 @@ typedef struct {
     int32_t flags;              /* ERI_PLAN_ALL_QUARTETS or 0 */
     double schwarz_threshold;   /* with ERI_PLAN_ALL_QUARTETS: keep (ab|cd) with Q_ab Q_cd >= this */
     int64_t ring_bytes;         /* with ERI_PLAN_ALL_QUARTETS: bound on the output held (0 = all) */
-    int64_t chunk_quartets;     /* with ERI_PLAN_ALL_QUARTETS: quartets per launch chunk (0 = 2^25) */
+    int64_t chunk_quartets;     /* with ERI_PLAN_ALL_QUARTETS: quartets per launch chunk (0 = 2^25);
+                                   for every plan also a bound on the quartets of one eri_backward
+                                   pass (0 = the library's choice) */
+    int32_t scale_block;        /* quartets per scale block G (0 or 1 = one scale per quartet, the
+                                   paper's choice, Sec. II-D); G > 1: G consecutive quartets of a
+                                   class in plan order share one b_max and eps (eq. 9 over the
+                                   block), explicit plans only */
+    int32_t reserved_opt;
 } eri_plan_opts;
 
 typedef struct {
@@ -101,6 +110,12 @@ typedef struct {
                                      3 two-wavefront slots (suffix _w2), 4 bra and ket exchanged
                                      (suffix _s), 5 two-wavefront slots at half the registers
                                      (suffix _w2o2) */
+    int32_t class_fp32[256];      /* 1: the class's recurrences run in FP32 (FP32-mixed plans, classes
+                                     whose FP32 error was measured within 1e-8 Ha); 0: FP64 */
+    int32_t scale_block;          /* G of eri_plan_opts (1 = per quartet) */
+    int32_t reserved2;
+    int64_t class_scale_off[257]; /* first scale of each class: class c holds
+                                     ceil(class_ring[c] / G) scales */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
@@ -117,7 +132,8 @@ typedef struct {
  * j of class c lands in slot j mod class_ring[c]); opts->ring_bytes bounds the
  * total (codes, or FP64 values when bits = 0).
  * Returns ERI_EINVAL for null pointers or indices outside [0, n_shells),
- * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K] or a bad `bits`,
+ * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K], a bad `bits`, or
+ * scale_block > 1 with ERI_PLAN_ALL_QUARTETS,
  * ERI_ENOMEM / ERI_EHIP on allocation or upload failure.  On success *out owns
  * all device memory of the plan until eri_plan_destroy(). */
 int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* L, const int32_t* K,
@@ -141,11 +157,16 @@ int eri_plan_quartets(const eri_plan* plan, int32_t class_id, int64_t first, int
 
 /* Compute every quartet of the plan on `stream` (Sec. II-B..II-D): contracted
  * ERIs; when out_eri is not NULL they are written as FP64; when the plan has
- * bits > 0 and out_codes is not NULL, each quartet is compressed with its own
- * b_max (eqs. 9-10) into codes plus one FP64 scale eps (out_scales, required
- * with codes).  Device pointers, plan order; the arrays hold
- * class_eri_off[256] values/codes and class_quartet_off[256] scales (equal to
- * n_eri and n_quartets unless a ring bound applies).
+ * bits > 0 and out_codes is not NULL, each scale block (one quartet, or G
+ * consecutive quartets of a class with scale_block = G) is compressed with
+ * its own b_max (eqs. 9-10) into codes plus one FP64 scale eps (out_scales,
+ * required with codes).  Device pointers, plan order; the arrays hold
+ * class_eri_off[256] values/codes and class_scale_off[256] scales (equal to
+ * n_eri and n_quartets unless a ring bound or G > 1 applies).  With G = 1 the
+ * codes are written by the ERI kernels themselves; with G > 1 a block spans
+ * several workgroups, so the class's FP64 values are written first (to
+ * out_eri, or to a staging buffer the plan holds) and a second kernel
+ * compresses each block.
  * Returns ERI_EINVAL if no output is requested.  For ERI_PLAN_ALL_QUARTETS
  * plans all launches are captured once into a hipGraph (per output pointer
  * set) and replayed as a single graph launch. */
@@ -215,8 +236,10 @@ int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_
  * g(a+1) - a g(a-1); exponent: N[(3/4 + L/2)/alpha g(a) - sum g(a+2)]) as
  * contracted ERIs of derived shells computed by the FP64 class kernels,
  * whatever the plan's precision; the fourth centre's derivative follows from
- * translation invariance.  Accumulation uses FP64 atomics, so the summation
- * order (and the last bits) may vary between calls.
+ * translation invariance.  Gradient accumulation uses FP64 atomics, so the
+ * summation order (and the last bits of the gradients) may vary between
+ * calls; L is summed in a fixed order with compensated (two-sum) arithmetic,
+ * so *energy is the same on every call with the same inputs.
  * Returns ERI_EUNSUPPORTED when a shell of the plan has L > 2 (the exponent
  * derivative of an L shell needs L+2 integrals, computed up to g),
  * ERI_ESTATE for dl_deri with a plan whose output ring holds fewer quartets
@@ -246,6 +269,36 @@ int eri_pack(int32_t bits, const void* codes, int64_t n_blocks, const int64_t* b
  * decompressed values code * scales[b] (eq. 11; out, optional, needs scales). */
 int eri_unpack(int32_t bits, const void* packed, int64_t n_blocks, const int64_t* block_off,
                const int64_t* word_off, const double* scales, int32_t* codes, double* out, void* stream);
+
+/* Host-side decompression (eq. 11), for the consumer of compressed ERIs once
+ * the codes are in host memory (the paper decompresses on the host, Sec.
+ * II-D).  All pointers are HOST memory; blocks as in eri_decompress:
+ * out[i] = codes[i] * scales[b] for i in block b (codes: int8/int16/int32
+ * containers for bits <= 8/16/32).  n_threads host threads (0 = all).
+ * ERI_EUNSUPPORTED for bits outside [2, 32], ERI_EINVAL for null pointers,
+ * ERI_ENOMEM if threads cannot be started. */
+int eri_decompress_host(int32_t bits, const void* codes, const double* scales, int64_t n_blocks,
+                        const int64_t* block_off, double* out, int32_t n_threads);
+
+/* Host-side reverse of eri_pack (same stream layout and arguments as
+ * eri_unpack, all in HOST memory): int32 codes (codes, optional) and/or
+ * decompressed values code * scales[b] (out, optional, needs scales).
+ * n_threads host threads (0 = all).  Errors as eri_decompress_host. */
+int eri_unpack_host(int32_t bits, const void* packed, int64_t n_blocks, const int64_t* block_off,
+                    const int64_t* word_off, const double* scales, int32_t* codes, double* out,
+                    int32_t n_threads);
+
+/* Replace the centres (xyz: 3 per shell, host) and/or the exponents (exps:
+ * host, the layout of eri_plan_create) of the plan's shell set, keeping its
+ * quartet set, its orientation choices and, for ERI_PLAN_ALL_QUARTETS plans,
+ * its Schwarz screening as they were decided at creation.  The pair tables
+ * (eq. 3 Gaussian products) are recomputed and uploaded (synchronous); the
+ * next eri_compute / eri_backward uses the new geometry.  This is what a
+ * geometry step or a finite-difference probe of the same quartet set needs.
+ * Either pointer may be NULL (that part unchanged), not both.
+ * ERI_EINVAL for a non-positive exponent (checked first: nothing changes),
+ * ERI_EHIP on upload failure. */
+int eri_plan_set_geometry(eri_plan* plan, const double* xyz, const double* exps);
 
 void eri_plan_destroy(eri_plan* plan);
 

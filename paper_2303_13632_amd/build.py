@@ -65,9 +65,12 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=None):
     if not os.path.exists(bt):
         gen_boys_table.write(bt)
     files, _ = codegen.generate(GEN, precisions=precisions, classes=classes)
-    deps = [os.path.join(CSRC, f) for f in ("eri_device.h", "eri_plan_types.h", "eri_dispatch.h",
-                                            "eri_internal.h")] + [bt]
-    srcs = files + [os.path.join(CSRC, "eri_lib.hip"), os.path.join(CSRC, "eri_backward.hip")]
+    # generated kernel TUs see the device headers only; the host TUs also the
+    # plan internals and the C ABI header
+    kdeps = [os.path.join(CSRC, f) for f in ("eri_device.h", "eri_plan_types.h", "eri_dispatch.h")] + [bt]
+    hdeps = kdeps + [os.path.join(CSRC, "eri_internal.h"), os.path.join(ROOT, "include", "eri.h")]
+    host = [os.path.join(CSRC, "eri_lib.hip"), os.path.join(CSRC, "eri_backward.hip")]
+    srcs = files + host
     jobs = jobs or min(16, os.cpu_count() or 4)
     objs = []
     t0 = time.time()
@@ -75,7 +78,7 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=None):
         futs = {}
         for s in srcs:
             obj = os.path.join(OBJ, os.path.basename(s) + ".o")
-            futs[ex.submit(_compile, s, obj, deps + [os.path.join(ROOT, "include", "eri.h")])] = s
+            futs[ex.submit(_compile, s, obj, hdeps if s in host else kdeps)] = s
         for fu in cf.as_completed(futs):
             obj, dt, did = fu.result()
             objs.append(obj)

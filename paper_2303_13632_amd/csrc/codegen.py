@@ -1077,6 +1077,10 @@ def emit_class(cp, prec, alt=False, occupancy=1):
         return name, emit_mode_T(cp, prec, name)[1]
     if occupancy > 1:
         name += "_o%d" % occupancy
+        if unsafe_half_register(cp, 16384):
+            raise ValueError("%s: two bra indices per lane at half the registers with the HRR staging in %d "
+                             "chunks is the form that returned wrong values on the GPU (see "
+                             "unsafe_half_register); it is not generated" % (name, lds_chunks(cp, 16384)))
         return name, emit_mode_W(cp, prec, name, lds_budget=16384, waves=occupancy)[1]
     return name, emit_mode_W(cp, prec, name)[1]
 
@@ -1102,17 +1106,26 @@ def swapped_variant(cp):
     return ClassPlan(*cp.user, perm=cp.perm[2:] + cp.perm[:2])
 
 
+def unsafe_half_register(cp, lds_budget):
+    """True for the one configuration known to give wrong results: two bra
+    indices per lane (an f-f bra), half the registers, and HRR staging in more
+    chunks than the 32 KB form needs.  The [ff|ff] kernel of that form (four
+    chunks; 256 VGPRs, no AGPRs, 2960 bytes of scratch spills per lane)
+    returned values off by up to 2.3e6 on the GPU, while the same generated
+    source run on the CPU through an emulation of the wavefront matched the
+    oracle.  No indexing, LDS-size or barrier fault was found by reading it;
+    the cause is not known, so the form is not generated."""
+    subs, EP = wave_layout(cp)
+    return len(subs) == 2 and lds_chunks(cp, lds_budget) > lds_chunks(cp, 32768)
+
+
 def occupancy_variant(cp):
     """Slot-mapped classes large enough to be register-bound also get a
     kernel limited to half the registers (two wavefronts per SIMD, half the
-    LDS staging).  Not for classes with two bra indices per lane whose
-    staging would need more chunks than a 32 KB one: an [ff|ff] kernel
-    staged in three or more chunks returned wrong values on the GPU while the
-    same source run on the CPU gave the right ones, a failure not understood."""
+    LDS staging), except in the form unsafe_half_register() excludes."""
     if cp.mode != "W" or cp.Ltot < 6:
         return False
-    subs, EP = wave_layout(cp)
-    return len(subs) == 1 or lds_chunks(cp, 16384) == lds_chunks(cp, 32768)
+    return not unsafe_half_register(cp, 16384)
 
 
 def alternate_mode(cp):
@@ -1166,17 +1179,34 @@ def variant_infos(cp, name, tag=TAG_DEFAULT):
     return [kernel_info_init(cp, name, tag=tag)]
 
 
+def mixed_fp32_classes():
+    """Class ids whose recurrences run in FP32 in FP32-mixed plans (the
+    measured table mixed_fp32_classes.json beside this file); the other classes
+    run their FP64 kernels in such plans.  FP32 Obara-Saika recurrences lose
+    digits to cancellation on long bonds with mixed exponents: beyond small
+    angular momenta they miss 1e-7 Ha (up to ~1e-3 Ha for [ff|ff]), and on this
+    hardware FP32 without packed instructions issues at the FP64 rate, so the
+    FP64 kernel costs those classes nothing in arithmetic rate."""
+    import json
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "mixed_fp32_classes.json")) as f:
+        return set(int(c) for c in json.load(f)["fp32_classes"])
+
+
 def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None, g_classes=True):
     """Write kernel sources (grouped `group` classes per file, each with a host
     registration function filling its entries of the kernel table) and the
     table TU; returns (list of source files, dict of ClassPlan).  `classes`
-    is a list of (La, Lb, Lc, Ld); by default the 256 s-f classes in every
-    precision plus, in FP64 only, the classes with one g shell."""
+    is a list of (La, Lb, Lc, Ld); by default the 256 s-f classes in FP64 and,
+    for the classes of mixed_fp32_classes(), in FP32-mixed, plus, in FP64
+    only, the classes with one g shell.  The FP32-mixed table holds the FP64
+    kernels of the other classes."""
     os.makedirs(outdir, exist_ok=True)
     overrides = overrides or {}
     if classes is None:
         classes = [class_of(c) for c in range(256)]
-    jobs = [(c, prec) for prec in precisions for c in classes]
+    fp32_ok = mixed_fp32_classes()
+    jobs = [(c, prec) for prec in precisions for c in classes
+            if prec != "mixed" or class_id(*c) in fp32_ok]
     if g_classes:
         jobs += [(c, "fp64") for c in G_CLASSES]
     plans = {}
@@ -1195,7 +1225,8 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
             parts.append(src)
             c5 = class_id5(*user)
             lines_ = reg.setdefault(prec, [])
-            lines_.append("    t[%d] = %s;" % (c5, kernel_info_init(cp, name)))
+            fp32 = ", 1}" if prec == "mixed" else ", 0}"
+            lines_.append("    t[%d] = %s;" % (c5, kernel_info_init(cp, name)[:-1] + fp32))
             infos = variant_infos(cp, name)
             am = alternate_mode(cp) if max(user) <= 3 else None
             if am is not None:
@@ -1228,7 +1259,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                     infos.append(w2_info(cp, wname + "o2", TAG_TWO_WAVES_OCC2))
             assert len(infos) <= MAXVAR, (user, len(infos))
             for k, info in enumerate(infos):
-                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
+                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info[:-1] + fp32))
         for prec, lines_ in reg.items():
             fname = "eri_register_%s_g%03d" % (prec, g // group)
             parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
@@ -1242,11 +1273,19 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5];")
     lines.append("static eri_kernel_info v_fp64[ERI_NCLASS5 * ERI_MAXVAR], v_mixed[ERI_NCLASS5 * ERI_MAXVAR];")
     lines.append("static std::once_flag g_once;")
+    routed = [class_id5(*c) for c in classes if class_id(*c) not in fp32_ok] if "mixed" in precisions else []
+    lines.append("// classes whose FP32-mixed entries are their FP64 kernels")
+    lines.append("static const int g_mixed_fp64[] = {%s};" % (", ".join(str(c) for c in routed) or "-1"))
     lines.append("static void fill()")
     lines.append("{")
     lines.append("    std::call_once(g_once, [] {")
     for prec, fname in regs:
         lines.append("        %s(%s);" % (fname, "g_fp64, v_fp64" if prec == "fp64" else "g_mixed, v_mixed"))
+    lines.append("        for (int c5 : g_mixed_fp64) {")
+    lines.append("            if (c5 < 0) continue;")
+    lines.append("            g_mixed[c5] = g_fp64[c5];")
+    lines.append("            for (int k = 0; k < ERI_MAXVAR; ++k) v_mixed[c5 * ERI_MAXVAR + k] = v_fp64[c5 * ERI_MAXVAR + k];")
+    lines.append("        }")
     lines.append("    });")
     lines.append("}")
     lines.append("const eri_kernel_info* eri_kernel_table(int precision)")

@@ -26,7 +26,12 @@
 // own slice of a partial-sum buffer (no atomics on global memory); one final
 // kernel adds the slices into the caller's arrays.  Gradients too large for
 // LDS fall back to global FP64 atomics.  Either way the order of the atomic
-// additions, and so the last bits of the sums, may vary between calls.
+// additions, and so the last bits of the gradient sums, may vary between
+// calls.  The scalar L itself is summed in a fixed order: every quartet's
+// contribution is written to a buffer and one workgroup adds a pass's buffer
+// with compensated (two-sum) arithmetic into a double-double running total,
+// so L is a deterministic function of the inputs (what finite differences of
+// L need).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -78,8 +83,10 @@ struct eri_bwd_state {
     int32_t* d_origin = nullptr;  // exponent items: quartet | (primitive << 24)
     void* d_scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
-    int64_t n_grad = 0;           // 3 n_shells + n_prims + 1 (energy)
+    int64_t n_grad = 0;           // 3 n_shells + n_prims
     double* d_part = nullptr;     // BWD_SLICES partial gradients (LDS mode)
+    double* d_eitem = nullptr;    // per quartet of a pass: its contribution to L
+    double* d_eacc = nullptr;     // running total of L: (high, low) double-double
     int32_t* h_pin = nullptr;     // pinned host word for scan totals
     std::vector<int8_t> var = std::vector<int8_t>(ERI_NCLASS5, -1);   // launch variant per derived class
     eri_item* d_usorted = nullptr;   // a pass's user items ordered by primitive-quartet count
@@ -93,7 +100,8 @@ void eri_bwd_free(eri_bwd_state* b)
     if (!b) return;
     void* ptrs[] = {b->d_pairs,  b->d_prims, b->d_dmap,   b->d_uall,     b->d_uitems,   b->d_ditems,
                     b->d_scratch, b->d_bf,    b->d_poff,   b->d_cnt,      b->d_off,      b->d_origin,
-                    b->d_scan_tmp, b->d_part, b->d_usorted, b->d_key,     b->d_sort_tmp};
+                    b->d_scan_tmp, b->d_part, b->d_usorted, b->d_key,     b->d_sort_tmp, b->d_eitem,
+                    b->d_eacc};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     if (b->h_pin) (void)hipHostFree(b->h_pin);
@@ -214,10 +222,10 @@ __global__ __launch_bounds__(256) void eri_bwd_zero_kernel(double* __restrict__ 
     for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) x[t] = 0.0;
 }
 
-// grad_c / grad_e / energy += sum over slices, in slice order.
+// grad_c / grad_e += sum over slices, in slice order.
 __global__ __launch_bounds__(256) void eri_bwd_reduce_kernel(const double* __restrict__ part, int64_t n_grad,
                                                              int64_t ns3, double* __restrict__ grad_c,
-                                                             double* __restrict__ grad_e, double* __restrict__ energy)
+                                                             double* __restrict__ grad_e)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= n_grad) return;
@@ -225,10 +233,59 @@ __global__ __launch_bounds__(256) void eri_bwd_reduce_kernel(const double* __res
     for (int b = 0; b < BWD_SLICES; ++b) v += part[(int64_t)b * n_grad + t];
     if (t < ns3) {
         if (grad_c) grad_c[t] += v;
-    } else if (t < n_grad - 1) {
-        if (grad_e) grad_e[t - ns3] += v;
-    } else if (energy) {
-        energy[0] += v;
+    } else if (grad_e) {
+        grad_e[t - ns3] += v;
+    }
+}
+
+// Error-free sum of two doubles (Knuth's two-sum): s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e)
+{
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// acc (double-double) += sum of x[0 .. n), in a fixed order: thread t adds
+// x[t], x[t + 256], ... with compensation, then a fixed pairwise tree
+// combines the 256 partial (sum, error) pairs.  One workgroup of 256.
+__global__ __launch_bounds__(256) void eri_bwd_energy_sum_kernel(const double* __restrict__ x, int64_t n,
+                                                                 double* __restrict__ acc)
+{
+    __shared__ double s_hi[256], s_lo[256];
+    double hi = 0.0, lo = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        double e;
+        two_sum(hi, x[i], hi, e);
+        lo += e;
+    }
+    s_hi[threadIdx.x] = hi;
+    s_lo[threadIdx.x] = lo;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            double s, e;
+            two_sum(s_hi[threadIdx.x], s_hi[threadIdx.x + w], s, e);
+            s_hi[threadIdx.x] = s;
+            s_lo[threadIdx.x] = s_lo[threadIdx.x] + s_lo[threadIdx.x + w] + e;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double s, e;
+        two_sum(acc[0], s_hi[0], s, e);
+        const double l = acc[1] + s_lo[0] + e;
+        two_sum(s, l, acc[0], acc[1]);
+    }
+}
+
+// energy[0] += the running total of L; zeroes the total.
+__global__ void eri_bwd_energy_out_kernel(double* __restrict__ acc, double* __restrict__ energy)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        energy[0] += acc[0] + acc[1];
+        acc[0] = 0.0;
+        acc[1] = 0.0;
     }
 }
 
@@ -247,7 +304,7 @@ struct bwd_contract_args {
     const int64_t* poff;
     double* grad_c;             // global atomics mode
     double* grad_e;
-    double* energy;
+    double* eitem;              // base kind: per-item contributions to L
     double* part;               // LDS mode: slices of n_grad partial sums, or null
     int64_t n_grad;
     int64_t ns3;                // 3 n_shells
@@ -351,9 +408,8 @@ __global__ __launch_bounds__(256) void eri_bwd_contract_kernel(bwd_contract_args
         acc0 *= w; acc1 *= w; acc2 *= w;
         double* gc = lds ? s_g : A.grad_c;
         double* ge = lds ? s_g + A.ns3 : A.grad_e;
-        double* en = lds ? s_g + A.n_grad - 1 : A.energy;
         if (A.kind == DK_BASE) {
-            atomicAdd(en, acc0);
+            A.eitem[j] = acc0;
         } else if (A.kind == DK_PLUS || A.kind == DK_MINUS) {
             const double v[3] = {acc0, acc1, acc2};
             for (int x = 0; x < 3; ++x) {
@@ -547,10 +603,11 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
     // passes of small classes take up to BWD_CHUNK_MAX quartets; larger derived
     // blocks shorten the pass so that one kind's blocks fit the scratch
     st->chunk_cap = std::max<int64_t>(1, std::min(maxcount, BWD_CHUNK_MAX));
+    if (p->pass_cap > 0) st->chunk_cap = std::min(st->chunk_cap, p->pass_cap);
     st->scratch_elems = std::min(BWD_SCRATCH_MAX, st->chunk_cap * maxnd * st->kmax_all);
     int64_t nprim_all = 0;
     for (int64_t s = 0; s < ns; ++s) nprim_all = std::max<int64_t>(nprim_all, orig.off[s] + orig.K[s]);
-    st->n_grad = 3 * ns + nprim_all + 1;
+    st->n_grad = 3 * ns + nprim_all;
     int rc = ERI_OK;
     auto up = [&](void** dst, const void* src, size_t bytes) {
         if (rc == ERI_OK) rc = upload(p, dst, src, bytes);
@@ -586,6 +643,8 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
     }
     up((void**)&st->d_sort_tmp, nullptr, std::max<size_t>(st->sort_tmp_bytes, 64));
     if (st->n_grad <= BWD_LDS_MAX) up((void**)&st->d_part, nullptr, (size_t)BWD_SLICES * st->n_grad * sizeof(double));
+    up((void**)&st->d_eitem, nullptr, (size_t)st->chunk_cap * sizeof(double));
+    up((void**)&st->d_eacc, nullptr, 2 * sizeof(double));
     if (rc == ERI_OK) {
         hipError_t e = hipHostMalloc((void**)&st->h_pin, 2 * sizeof(int32_t), hipHostMallocDefault);
         if (e != hipSuccess) {
@@ -733,8 +792,8 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     ca.poff = st->d_poff;
     ca.grad_c = call.grad_c;
     ca.grad_e = call.grad_e;
-    ca.energy = call.energy;
-    ca.part = call.lds ? st->d_part : nullptr;
+    ca.eitem = st->d_eitem;
+    ca.part = call.lds && kind != DK_BASE ? st->d_part : nullptr;
     ca.n_grad = st->n_grad;
     ca.ns3 = 3 * (int64_t)p->sh_L.size();
     for (int x = 0; x < 4; ++x) ca.L[x] = L[x];
@@ -746,9 +805,13 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     ca.degen = p->batched ? 1 : 0;
     const int64_t per_block = 256 / G;
     const int64_t blocks = std::min<int64_t>(BWD_SLICES, (m + per_block - 1) / per_block);
-    const size_t lds = call.lds ? (size_t)st->n_grad * sizeof(double) : 0;
+    const size_t lds = ca.part ? (size_t)st->n_grad * sizeof(double) : 0;
     hipLaunchKernelGGL(eri_bwd_contract_kernel, dim3((unsigned)blocks), dim3(256), lds, strm, ca);
     ERI_HIP_TRY(hipGetLastError());
+    if (kind == DK_BASE) {
+        hipLaunchKernelGGL(eri_bwd_energy_sum_kernel, dim3(1), dim3(256), 0, strm, st->d_eitem, m, st->d_eacc);
+        ERI_HIP_TRY(hipGetLastError());
+    }
     return ERI_OK;
 }
 
@@ -878,11 +941,19 @@ extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, co
                            (int64_t)BWD_SLICES * st->n_grad);
         if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
     }
+    if (rc == ERI_OK && energy) {
+        hipLaunchKernelGGL(eri_bwd_zero_kernel, dim3(1), dim3(256), 0, strm, st->d_eacc, (int64_t)2);
+        if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
+    }
     for (int c = 0; c < 256 && rc == ERI_OK; ++c)
         if (p->class_count[c]) rc = run_class(p, st, c, strm, call);
     if (rc == ERI_OK && call.lds) {
         hipLaunchKernelGGL(eri_bwd_reduce_kernel, dim3((unsigned)((st->n_grad + 255) / 256)), dim3(256), 0, strm,
-                           st->d_part, st->n_grad, 3 * (int64_t)p->sh_L.size(), grad_centers, grad_exps, energy);
+                           st->d_part, st->n_grad, 3 * (int64_t)p->sh_L.size(), grad_centers, grad_exps);
+        if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
+    }
+    if (rc == ERI_OK && energy) {
+        hipLaunchKernelGGL(eri_bwd_energy_out_kernel, dim3(1), dim3(64), 0, strm, st->d_eacc, energy);
         if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
     }
     if (cur != p->device) (void)hipSetDevice(cur);

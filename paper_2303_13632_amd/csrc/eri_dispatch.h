@@ -14,11 +14,13 @@ struct eri_kernel_info {
     int32_t tag;         // generated kernel: 0 default, 1 alternate mapping, 2 half-register (2 waves/SIMD),
                          // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged, 5 two wavefronts
                          // at half the registers
+    int32_t fp32;        // 1: VRR/HRR in FP32 (FP32-mixed kernel); 0: FP64
 };
 
 // Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by
 // La*125 + Lb*25 + Lc*5 + Ld (angular momenta up to 4); entries of classes
-// without a kernel have fn == nullptr.
+// without a kernel have fn == nullptr.  The FP32-mixed table holds FP64
+// kernels (fp32 == 0) for the classes whose FP32 recurrences miss 1e-7 Ha.
 #define ERI_NCLASS5 625
 const eri_kernel_info* eri_kernel_table(int precision);
 

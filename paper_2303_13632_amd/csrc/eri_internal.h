@@ -122,6 +122,7 @@ struct eri_plan {
     std::vector<int64_t> pos;       // explicit plans: user quartet -> plan position
     std::vector<int64_t> eri_off;   // explicit plans: user quartet -> first ERI
     std::vector<int32_t> quartets;  // explicit plans: user quartets in plan order
+    std::vector<uint64_t> pair_keys;  // explicit plans: (a << 32) | b of each pair record, in table order
     int64_t class_count[256] = {};
     int64_t class_ring[256] = {};
     int64_t class_qoff[257] = {};
@@ -142,6 +143,10 @@ struct eri_plan {
     int64_t* d_seg_off = nullptr;
     int32_t* d_seg_p1 = nullptr;
     int64_t chunk_cap = 0;
+    int64_t pass_cap = 0;               // opts->chunk_quartets: bound on an adjoint pass (0 = default)
+    int32_t scale_block = 1;            // quartets per scale block
+    int64_t class_soff[257] = {};       // first scale of each class
+    double* d_stage = nullptr;          // scale_block > 1: FP64 values of one class (when out_eri is NULL)
     double schwarz = 0.0;
     std::vector<double> pair_q;
     hipGraphExec_t graph = nullptr;

@@ -10,7 +10,10 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
+#include <mutex>
+#include <system_error>
 #include <new>
 #include <string>
 #include <numeric>
@@ -149,6 +152,7 @@ static void plan_free(eri_plan* p)
     if (p->d_items) (void)hipFree(p->d_items);
     if (p->d_seg_off) (void)hipFree(p->d_seg_off);
     if (p->d_seg_p1) (void)hipFree(p->d_seg_p1);
+    if (p->d_stage) (void)hipFree(p->d_stage);
     if (p->bwd) eri_bwd_free(p->bwd);
     if (cur != p->device) (void)hipSetDevice(cur);
     delete p;
@@ -211,7 +215,7 @@ static int create_explicit(eri_plan* p, const shell_set& s, const int32_t* quart
             ket[t] = (int32_t)(std::lower_bound(uniq.begin(), uniq.end(), keys[2 * t + 1]) - uniq.begin());
         }
     });
-    std::vector<uint64_t>().swap(uniq);
+    p->pair_keys.swap(uniq);
     std::vector<uint64_t>().swap(keys);
     // plan order: class (8 bits), bra and ket primitive counts (9 bits each),
     // then the user index (32 bits): a plain sort is stable in user order
@@ -487,8 +491,11 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     if (rc) return rc;
     if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED) return ERI_EUNSUPPORTED;
     if (opts->bits != 0 && (opts->bits < 2 || opts->bits > 32)) return ERI_EUNSUPPORTED;
-    if (!(opts->schwarz_threshold >= 0.0) || opts->ring_bytes < 0 || opts->chunk_quartets < 0) return ERI_EINVAL;
+    if (!(opts->schwarz_threshold >= 0.0) || opts->ring_bytes < 0 || opts->chunk_quartets < 0 ||
+        opts->scale_block < 0)
+        return ERI_EINVAL;
     const bool batched = (opts->flags & ERI_PLAN_ALL_QUARTETS) != 0;
+    if (batched && opts->scale_block > 1) return ERI_EUNSUPPORTED;
     if (batched) {
         if (quartets || n_quartets) return ERI_EINVAL;
     } else {
@@ -502,6 +509,8 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     p->precision = opts->precision;
     p->bits = opts->bits;
     p->code_bytes = opts->bits == 0 ? 0 : opts->bits <= 8 ? 1 : opts->bits <= 16 ? 2 : 4;
+    p->pass_cap = opts->chunk_quartets;
+    p->scale_block = std::max(1, opts->scale_block);
     if (opts->bits) {
         p->qmax = (double)((((int64_t)1) << (opts->bits - 1)) - 1);
         p->cn = 1.0 / p->qmax;
@@ -524,6 +533,15 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
         p->sh_exps.assign(exps, exps + nprim_all);
         p->sh_coefs.assign(coefs, coefs + nprim_all);
         rc = batched ? create_batched(p, s, opts) : create_explicit(p, s, quartets, n_quartets);
+        // scale blocks: G consecutive quartets of a class share one scale
+        const int64_t G = p->scale_block;
+        int64_t stage = 0;
+        p->class_soff[0] = 0;
+        for (int c = 0; c < 256; ++c) {
+            p->class_soff[c + 1] = p->class_soff[c] + (p->class_ring[c] + G - 1) / G;
+            stage = std::max(stage, p->class_eoff[c + 1] - p->class_eoff[c]);
+        }
+        if (rc == ERI_OK && G > 1 && p->bits > 0) rc = upload(p, (void**)&p->d_stage, nullptr, (size_t)stage * sizeof(double));
     } catch (const std::bad_alloc&) {
         rc = ERI_ENOMEM;
     }
@@ -565,11 +583,14 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
         while (nv < ERI_MAXVAR && var[class_id5_of(c) * ERI_MAXVAR + nv].fn) ++nv;
         info->class_n_variants[c] = nv;
         info->class_tag[c] = ki.tag;
+        info->class_fp32[c] = ki.fp32;
     }
     for (int c = 0; c <= 256; ++c) {
         info->class_eri_off[c] = p->class_eoff[c];
         info->class_quartet_off[c] = p->class_qoff[c];
+        info->class_scale_off[c] = p->class_soff[c];
     }
+    info->scale_block = p->scale_block;
     return ERI_OK;
 }
 
@@ -619,7 +640,7 @@ static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, vo
     a.prims = p->d_prims;
     a.out_eri = out_eri ? out_eri + p->class_eoff[c] : nullptr;
     a.out_codes = out_codes ? (void*)((char*)out_codes + p->class_eoff[c] * p->code_bytes) : nullptr;
-    a.out_scales = out_scales ? out_scales + p->class_qoff[c] : nullptr;
+    a.out_scales = out_scales ? out_scales + p->class_soff[c] : nullptr;
     a.cn = p->cn;
     a.qmax = p->qmax;
     a.code_bytes = p->code_bytes;
@@ -676,7 +697,31 @@ static const eri_kernel_info& class_kernel(const eri_plan* p, int c)
     return kernel_table(p->precision)[c5];
 }
 
-static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, void* out_codes, double* out_scales)
+// Compression of one class's FP64 values in blocks of S consecutive values
+// (G quartets): one 256-thread workgroup per block; eq. 9 (b_max by an exact
+// max reduction) and eq. 10 (the same quantiser as the fused kernels).
+template <typename CT>
+__global__ __launch_bounds__(256) void eri_compress_blocks_kernel(const double* __restrict__ x, int64_t n, int64_t S,
+                                                                  CT* __restrict__ codes, double* __restrict__ scales,
+                                                                  double cn, double qmax)
+{
+    __shared__ double s_m[4];
+    const int64_t lo = (int64_t)blockIdx.x * S;
+    const int64_t hi = lo + S < n ? lo + S : n;
+    double m = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) m = fmax(m, fabs(x[i]));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = fmax(fmax(s_m[0], s_m[1]), fmax(s_m[2], s_m[3]));
+    const double eps = m * cn;
+    const double inv = eri_inverse_scale(eps);
+    if (threadIdx.x == 0) scales[blockIdx.x] = eps;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) codes[i] = (CT)eri_quantize(x[i], eps, inv, qmax);
+}
+
+static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, void* out_codes, double* out_scales,
+                        eri_item* item_buf = nullptr)
 {
     const int64_t n = p->class_count[c];
     if (n == 0) return ERI_OK;
@@ -687,7 +732,28 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
         ERI_TRY(orient_items(p, c, ki, st));
         a.items = p->d_items + p->class_qoff[c];
         a.n_items = n;
-        return launch_items(ki, a, st);
+        if (p->scale_block == 1 || !out_codes) return launch_items(ki, a, st);
+        // scale blocks of G quartets: FP64 values first, then one workgroup per block
+        double* vals = out_eri ? a.out_eri : p->d_stage;
+        void* codes = a.out_codes;
+        double* scales = a.out_scales;
+        a.out_eri = vals;
+        a.out_codes = nullptr;
+        a.out_scales = nullptr;
+        ERI_TRY(launch_items(ki, a, st));
+        const int64_t nv = p->class_eoff[c + 1] - p->class_eoff[c];
+        const int64_t S = (int64_t)p->scale_block * ki.n_eriq;
+        const int64_t nb = (n + p->scale_block - 1) / p->scale_block;
+        if (nb > INT32_MAX) return ERI_EUNSUPPORTED;
+        const dim3 g((unsigned)nb), b(256);
+        if (p->code_bytes == 1)
+            hipLaunchKernelGGL(eri_compress_blocks_kernel<int8_t>, g, b, 0, st, vals, nv, S, (int8_t*)codes, scales, p->cn, p->qmax);
+        else if (p->code_bytes == 2)
+            hipLaunchKernelGGL(eri_compress_blocks_kernel<int16_t>, g, b, 0, st, vals, nv, S, (int16_t*)codes, scales, p->cn, p->qmax);
+        else
+            hipLaunchKernelGGL(eri_compress_blocks_kernel<int32_t>, g, b, 0, st, vals, nv, S, (int32_t*)codes, scales, p->cn, p->qmax);
+        ERI_HIP_TRY(hipGetLastError());
+        return ERI_OK;
     }
     const auto sbeg = p->h_seg_off.begin();
     for (const auto& b : p->bclass) {
@@ -699,10 +765,11 @@ static int launch_class(eri_plan* p, int c, hipStream_t st, double* out_eri, voi
         const int64_t s0 = (int64_t)(std::upper_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q0) - sbeg) - 1;
         const int64_t s1 = (int64_t)(std::lower_bound(sbeg + bc->seg_lo, sbeg + bc->seg_hi, q1) - sbeg);
         if (s1 - s0 > INT32_MAX) return ERI_EUNSUPPORTED;
+        eri_item* items = item_buf ? item_buf : p->d_items;
         hipLaunchKernelGGL(eri_expand_kernel, dim3((unsigned)(s1 - s0)), dim3(256), 0, st, p->d_seg_off, p->d_seg_p1,
-                           s0, bc->ket_lo, q0, q1, kernel_swap(ki) ? 1 : 0, p->d_items);
+                           s0, bc->ket_lo, q0, q1, kernel_swap(ki) ? 1 : 0, items);
         ERI_HIP_TRY(hipGetLastError());
-        a.items = p->d_items;
+        a.items = items;
         a.n_items = q1 - q0;
         a.qbase = bc->qoff + q0;
         ERI_TRY(launch_items(ki, a, st));
@@ -1169,6 +1236,147 @@ extern "C" int eri_unpack(int32_t bits, const void* packed, int64_t n_blocks, co
                        (const uint64_t*)packed, block_off, word_off, scales, n_blocks, bits, codes, out);
     ERI_HIP_TRY(hipGetLastError());
     return ERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side decompression (eq. 11 on the host, where the consumer of the
+// compressed ERIs runs): blocks are split over host threads.
+// ---------------------------------------------------------------------------
+static void host_blocks(int64_t n_blocks, int32_t n_threads, const std::function<void(int64_t, int64_t)>& f)
+{
+    int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+    nt = (int)std::min<int64_t>(nt, std::max<int64_t>(1, n_blocks / 64));
+    if (nt <= 1) {
+        f(0, n_blocks);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n_blocks + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t lo = t * chunk, hi = std::min(n_blocks, lo + chunk);
+        if (lo < hi) th.emplace_back(f, lo, hi);
+    }
+    for (auto& x : th) x.join();
+}
+
+template <typename CT>
+static void host_decompress(const CT* codes, const double* scales, const int64_t* off, int64_t lo, int64_t hi,
+                            double* out)
+{
+    for (int64_t b = lo; b < hi; ++b) {
+        const double eps = scales[b];
+        for (int64_t i = off[b]; i < off[b + 1]; ++i) out[i] = (double)codes[i] * eps;
+    }
+}
+
+extern "C" int eri_decompress_host(int32_t bits, const void* codes, const double* scales, int64_t n_blocks,
+                                   const int64_t* block_off, double* out, int32_t n_threads)
+{
+    if (bits < 2 || bits > 32) return ERI_EUNSUPPORTED;
+    if (n_blocks < 0 || (n_blocks > 0 && (!codes || !scales || !block_off || !out))) return ERI_EINVAL;
+    try {
+        host_blocks(n_blocks, n_threads, [&](int64_t lo, int64_t hi) {
+            if (bits <= 8)
+                host_decompress((const int8_t*)codes, scales, block_off, lo, hi, out);
+            else if (bits <= 16)
+                host_decompress((const int16_t*)codes, scales, block_off, lo, hi, out);
+            else
+                host_decompress((const int32_t*)codes, scales, block_off, lo, hi, out);
+        });
+    } catch (const std::system_error&) {
+        return ERI_ENOMEM;
+    }
+    return ERI_OK;
+}
+
+extern "C" int eri_unpack_host(int32_t bits, const void* packed, int64_t n_blocks, const int64_t* block_off,
+                               const int64_t* word_off, const double* scales, int32_t* codes, double* out,
+                               int32_t n_threads)
+{
+    if (bits < 2 || bits > 32) return ERI_EUNSUPPORTED;
+    if (n_blocks < 0 || (n_blocks > 0 && (!packed || !block_off || !word_off || (!codes && !out) || (out && !scales))))
+        return ERI_EINVAL;
+    const uint64_t* w = (const uint64_t*)packed;
+    const int per = 512 / bits;
+    const int sh = 64 - bits;
+    try {
+        host_blocks(n_blocks, n_threads, [&](int64_t lo, int64_t hi) {
+            for (int64_t b = lo; b < hi; ++b) {
+                const int64_t o = block_off[b], n = block_off[b + 1] - o;
+                const double eps = out ? scales[b] : 0.0;
+                const uint64_t* word = w + 8 * word_off[b];
+                int64_t k = 0;
+                for (int64_t i = 0; i < n; i += per, word += 8) {
+                    const int m = (int)std::min<int64_t>(per, n - i);
+                    for (int j = 0; j < m; ++j, ++k) {
+                        const int bit = j * bits, q = bit >> 6, r = bit & 63;
+                        uint64_t v = word[q] >> r;
+                        if (r + bits > 64) v |= word[q + 1] << (64 - r);
+                        const int32_t c = (int32_t)((int64_t)(v << sh) >> sh);
+                        if (codes) codes[o + k] = c;
+                        if (out) out[o + k] = (double)c * eps;
+                    }
+                }
+            }
+        });
+    } catch (const std::system_error&) {
+        return ERI_ENOMEM;
+    }
+    return ERI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// New centres and exponents for an existing plan (same quartets)
+// ---------------------------------------------------------------------------
+extern "C" int eri_plan_set_geometry(eri_plan* p, const double* xyz, const double* exps)
+{
+    if (!p || (!xyz && !exps)) return ERI_EINVAL;
+    const int64_t ns = (int64_t)p->sh_L.size();
+    if (exps)
+        for (size_t i = 0; i < p->sh_exps.size(); ++i)
+            if (!(exps[i] > 0.0)) return ERI_EINVAL;
+    int cur = 0;
+    ERI_HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
+    int rc = ERI_OK;
+    try {
+        if (xyz) std::copy(xyz, xyz + 3 * ns, p->sh_xyz.begin());
+        if (exps) std::copy(exps, exps + p->sh_exps.size(), p->sh_exps.begin());
+        const shell_set s{ns, p->sh_L.data(), p->sh_K.data(), p->sh_xyz.data(), p->sh_off.data(), p->sh_exps.data(),
+                          p->sh_coefs.data()};
+        std::vector<uint64_t> keys;
+        if (p->batched) {
+            keys.resize(p->h_pairs.size());
+            for (size_t i = 0; i < keys.size(); ++i)
+                keys[i] = ((uint64_t)(uint32_t)p->h_pairs[i].sa << 32) | (uint32_t)p->h_pairs[i].sb;
+        }
+        std::vector<eri_shell_pair> pairs;
+        std::vector<eri_prim_pair> prims;
+        build_pair_tables(s, p->batched ? keys : p->pair_keys, pairs, prims);
+        if ((int64_t)pairs.size() != p->n_pairs || (int64_t)prims.size() != p->n_prims) {
+            rc = ERI_ESTATE;
+        } else {
+            hipError_t e = hipSuccess;
+            if (!pairs.empty())
+                e = hipMemcpy(p->d_pairs, pairs.data(), pairs.size() * sizeof(eri_shell_pair), hipMemcpyHostToDevice);
+            if (e == hipSuccess && !prims.empty())
+                e = hipMemcpy(p->d_prims, prims.data(), prims.size() * sizeof(eri_prim_pair), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                g_last_hip = (int)e;
+                rc = ERI_EHIP;
+            }
+            if (p->batched) p->h_pairs.swap(pairs);
+        }
+    } catch (const std::bad_alloc&) {
+        rc = ERI_ENOMEM;
+    }
+    // the adjoint's derived tables follow the geometry: rebuilt at the next call
+    if (p->bwd) {
+        eri_bwd_free(p->bwd);
+        p->bwd = nullptr;
+    }
+    if (cur != p->device) (void)hipSetDevice(cur);
+    return rc;
 }
 
 extern "C" void eri_plan_destroy(eri_plan* p) { plan_free(p); }

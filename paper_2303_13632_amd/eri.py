@@ -43,7 +43,8 @@ class PlanOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("bits", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("schwarz_threshold", ctypes.c_double), ("ring_bytes", ctypes.c_int64),
-                ("chunk_quartets", ctypes.c_int64)]
+                ("chunk_quartets", ctypes.c_int64), ("scale_block", ctypes.c_int32),
+                ("reserved_opt", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -57,7 +58,9 @@ class PlanInfo(ctypes.Structure):
                 ("class_quartet_off", ctypes.c_int64 * 257), ("class_flops", ctypes.c_double * 256),
                 ("class_variant", ctypes.c_int32 * 256), ("class_mode", ctypes.c_int32 * 256),
                 ("class_block", ctypes.c_int32 * 256), ("class_per_block", ctypes.c_int32 * 256),
-                ("class_n_variants", ctypes.c_int32 * 256), ("class_tag", ctypes.c_int32 * 256)]
+                ("class_n_variants", ctypes.c_int32 * 256), ("class_tag", ctypes.c_int32 * 256),
+                ("class_fp32", ctypes.c_int32 * 256), ("scale_block", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32), ("class_scale_off", ctypes.c_int64 * 257)]
 
 
 _vp = ctypes.c_void_p
@@ -88,6 +91,9 @@ def load():
     lib.eri_plan_set_variants.argtypes = [_vp, _i32p]
     lib.eri_pack.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int64, _vp, _vp]
     lib.eri_unpack.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.eri_plan_set_geometry.argtypes = [_vp, _vp, _vp]
+    lib.eri_decompress_host.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp, _vp, ctypes.c_int32]
+    lib.eri_unpack_host.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32]
     lib.eri_plan_destroy.argtypes = [_vp]
     lib.eri_plan_destroy.restype = None
     lib.eri_status_string.argtypes = [ctypes.c_int]
@@ -134,7 +140,7 @@ class Plan:
     `schwarz`; its outputs form per-class rings bounded by `ring_bytes`."""
 
     def __init__(self, shells, quartets, precision="fp64", bits=16, device=0, schwarz=1e-10,
-                 ring_bytes=0, chunk_quartets=0):
+                 ring_bytes=0, chunk_quartets=0, scale_block=1):
         lib = load()
         self.shells = shells
         self.batched = quartets is None
@@ -146,7 +152,7 @@ class Plan:
         self.device = int(device)
         opts = PlanOpts(PRECISIONS[precision], self.bits, self.device,
                         ERI_PLAN_ALL_QUARTETS if self.batched else 0, float(schwarz),
-                        int(ring_bytes), int(chunk_quartets))
+                        int(ring_bytes), int(chunk_quartets), int(scale_block), 0)
         h = _vp()
         L = np.ascontiguousarray(shells["L"], dtype=np.int32)
         K = np.ascontiguousarray(shells["K"], dtype=np.int32)
@@ -178,6 +184,8 @@ class Plan:
         self.class_ring = np.array(info.class_ring[:], dtype=np.int64)
         self.class_eri_off = np.array(info.class_eri_off[:], dtype=np.int64)
         self.class_quartet_off = np.array(info.class_quartet_off[:], dtype=np.int64)
+        self.class_scale_off = np.array(info.class_scale_off[:], dtype=np.int64)
+        self.scale_block = int(info.scale_block)
         self.class_flops = np.array(info.class_flops[:], dtype=np.float64)
         self._read_variants(info)
         self._pos = None
@@ -193,6 +201,7 @@ class Plan:
         self.class_per_block = np.array(info.class_per_block[:], dtype=np.int32)
         self.class_n_variants = np.array(info.class_n_variants[:], dtype=np.int32)
         self.class_tag = np.array(info.class_tag[:], dtype=np.int32)
+        self.class_fp32 = np.array(info.class_fp32[:], dtype=np.int32)
 
     def tune(self, sample_quartets=65536, trials=3, cache=None, stream=None):
         """eri_plan_tune: time each class's launch variants on a sample and keep
@@ -212,7 +221,7 @@ class Plan:
 
     def kernel_name(self, cid):
         """Name of the kernel a class launch uses (variant included)."""
-        prec = "mixed" if self.precision == "mixed" else "fp64"
+        prec = "mixed" if self.class_fp32[cid] else "fp64"
         return "eri_%s_c%03d%s" % (prec, cid, KERNEL_TAG_SUFFIX[int(self.class_tag[cid])])
 
     def layout(self):
@@ -232,8 +241,8 @@ class Plan:
 
     @property
     def out_blocks(self):
-        """Length of the scale array."""
-        return int(self.class_quartet_off[256])
+        """Length of the scale array (one scale per block of scale_block quartets)."""
+        return int(self.class_scale_off[256])
 
     def alloc(self, eri=True, codes=True):
         import torch
@@ -316,6 +325,25 @@ class Plan:
     def scales_to_user(self, scales):
         pos, _ = self.layout()
         return scales[pos]
+
+    def set_geometry(self, xyz=None, exps=None):
+        """eri_plan_set_geometry: new centres [n_shells, 3] and/or exponents for
+        the same quartet set (screening and orientation kept)."""
+        x = None if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1)
+        e = None if exps is None else np.ascontiguousarray(exps, dtype=np.float64).reshape(-1)
+        if x is not None and len(x) != 3 * len(self.shells["L"]):
+            raise ValueError("xyz needs 3 values per shell")
+        if e is not None and len(e) != len(self.shells["exps"]):
+            raise ValueError("exps needs one value per primitive")
+        _check(load().eri_plan_set_geometry(self._h, None if x is None else x.ctypes.data_as(ctypes.c_void_p),
+                                            None if e is None else e.ctypes.data_as(ctypes.c_void_p)),
+               "eri_plan_set_geometry")
+        sh = dict(self.shells)
+        if x is not None:
+            sh["xyz"] = x.reshape(-1, 3).copy()
+        if e is not None:
+            sh["exps"] = e.copy()
+        self.shells = sh
 
     def close(self):
         if getattr(self, "_h", None):
@@ -452,4 +480,35 @@ def unpack(bits, packed, block_off, word_off, scales=None, codes=True, values=Fa
     v = torch.empty(max(n, 1), dtype=torch.float64, device=packed.device) if values else None
     _check(load().eri_unpack(int(bits), _ptr(packed), nb, _ptr(block_off), _ptr(word_off), _ptr(scales), _ptr(c),
                              _ptr(v), _stream(stream)), "eri_unpack")
+    return c, v
+
+
+def _np_ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def decompress_host(bits, codes, scales, block_off, out=None, n_threads=0):
+    """eri_decompress_host on host numpy arrays: FP64 values code * eps."""
+    codes = np.ascontiguousarray(codes)
+    scales = np.ascontiguousarray(scales, dtype=np.float64)
+    block_off = np.ascontiguousarray(block_off, dtype=np.int64)
+    if out is None:
+        out = np.empty(len(codes), dtype=np.float64)
+    _check(load().eri_decompress_host(int(bits), _np_ptr(codes), _np_ptr(scales), len(block_off) - 1,
+                                      _np_ptr(block_off), _np_ptr(out), int(n_threads)), "eri_decompress_host")
+    return out
+
+
+def unpack_host(bits, packed, block_off, word_off, scales=None, codes=True, values=False, n_threads=0):
+    """eri_unpack_host on host numpy arrays: (int32 codes or None, values or None)."""
+    packed = np.ascontiguousarray(packed)
+    block_off = np.ascontiguousarray(block_off, dtype=np.int64)
+    word_off = np.ascontiguousarray(word_off, dtype=np.int64)
+    n = int(block_off[-1]) if len(block_off) else 0
+    c = np.empty(n, dtype=np.int32) if codes else None
+    v = np.empty(n, dtype=np.float64) if values else None
+    sc = None if scales is None else np.ascontiguousarray(scales, dtype=np.float64)
+    _check(load().eri_unpack_host(int(bits), _np_ptr(packed), len(block_off) - 1, _np_ptr(block_off),
+                                  _np_ptr(word_off), _np_ptr(sc), _np_ptr(c), _np_ptr(v), int(n_threads)),
+           "eri_unpack_host")
     return c, v

@@ -9,7 +9,9 @@ so for each s the 6-D integral factorises into three 2-D integrals over
 (x, x'), each a polynomial times a 2-D Gaussian.  Each 2-D integral is done
 exactly (up to rounding) by tensor Gauss-Hermite quadrature after completing
 the square; the s-integral is done by composite Gauss-Legendre quadrature after
-the map s = lam * t / (1 - t), t in [0, 1).  Used only on tiny s/p/d cases.
+the map s = lam * t / (1 - t), t in [0, 1).  Ten Gauss-Hermite points per
+axis integrate the polynomial factors exactly up to degree 19 in each of x and
+x', which covers four f shells (degree 6 in each).  Used on single quartets.
 """
 import numpy as np
 
@@ -63,7 +65,7 @@ def _axis_integrals(s, ea, eb, ec, ed, A, B, C, D, pows_ab, pows_cd, ngh=10):
 
 
 def primitive_block(L, R, ex, n_panels=48, n_gl=24):
-    """Unnormalised primitive ERIs for angular momenta L[4] (each <= 2),
+    """Unnormalised primitive ERIs for angular momenta L[4] (each <= 3),
     centres R[4,3], exponents ex[4]: all components row-major (a,b,c,d)."""
     La, Lb, Lc, Ld = [int(v) for v in L]
     R = np.asarray(R, dtype=np.float64)

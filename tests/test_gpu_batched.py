@@ -147,20 +147,20 @@ def test_graph_replays(molecule):
 
 def test_molecule_full_size_sampled():
     """The 384-atom molecule-like basis (1536 shells, every unique quartet with
-    Q_ab Q_cd >= 1e-10) in the benchmark's launch configuration: tuned
-    variants, one graph launch, int16 codes into a 48 GB ring.  Per class, 1024
-    seeded ring slots of the last window are decoded and checked against the
-    oracle's values of the quartets that own them: within half a step of the
-    oracle's value (plus the FP64 parity tolerance), and the scale within
-    rounding of the oracle's b_max * c_n."""
+    Q_ab Q_cd >= 1e-10) at full size, with the benchmark's kernels and launch
+    structure: tuned variants, one graph launch, int16 codes plus the FP64
+    values, into rings of 24 GB of codes (96 GB of values).  Per class, 1024
+    seeded ring slots of the last window are checked against the oracle's
+    values of the quartets that own them: FP64 values within 1e-12 Ha, codes
+    and scales bit-identical to the oracle's compressor fed those values, and
+    decoded values within half a step of the oracle's."""
     from paper_2303_13632_amd import eri
-    from parity_util import ABS_TOL, REL_TOL
     sh = W.molecule_basis(n_heavy=128, n_h=256)
-    plan = eri.Plan(sh, None, bits=16, schwarz=TAU, ring_bytes=int(48e9))
+    plan = eri.Plan(sh, None, bits=16, schwarz=TAU, ring_bytes=int(24e9))
     plan.tune(sample_quartets=65536, trials=2)
     print("molecule plan: %d quartets, %d ERIs" % (plan.n_quartets, plan.n_eri), flush=True)
-    _, c, s = plan.alloc(eri=False, codes=True)
-    plan.compute(None, c, s)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
     torch.cuda.synchronize()
     cn = 1.0 / (2 ** 15 - 1)
     rng = np.random.default_rng(384)
@@ -178,31 +178,22 @@ def test_molecule_full_size_sampled():
             scale_idx.append(int(plan.class_quartet_off[cid]) + int(slot))
             sizes.append(m)
     picks = np.array(picks, dtype=np.int32)
-    codes = c[torch.from_numpy(np.concatenate(code_idx)).cuda()].cpu().numpy().astype(np.float64)
+    idx = torch.from_numpy(np.concatenate(code_idx)).cuda()
+    vals = e[idx].cpu().numpy()
+    codes = c[idx].cpu().numpy().astype(np.int32)
     scales = s[torch.from_numpy(np.array(scale_idx)).cuda()].cpu().numpy()
+    del e, c, s, idx
+    torch.cuda.empty_cache()
     ref, ref_off, ref_sizes = O.eri(sh, picks, n_threads=THREADS)
     assert np.array_equal(ref_sizes, sizes)
     print("molecule sample: %d quartets over %d classes" % (len(picks), int((plan.class_quartets > 0).sum())),
           flush=True)
-    def violations(vals, voff):
-        bad = []
-        for t in range(len(picks)):
-            x = vals[voff[t]:voff[t] + sizes[t]]
-            q = codes[ref_off[t]:ref_off[t] + sizes[t]]
-            bmax, eps = np.abs(x).max(), scales[t]
-            tol = ABS_TOL + REL_TOL * np.abs(x)
-            ok = abs(eps - bmax * cn) <= (ABS_TOL + REL_TOL * bmax) * cn + 2 * np.spacing(eps)
-            ok = ok and np.all(np.abs(q * eps - x) <= eps / 2 + 4 * np.spacing(bmax) + tol)
-            if not ok:
-                bad.append(t)
-        return bad
-
-    bad = violations(ref, ref_off)
-    if bad:
-        # the double oracle's own rounding on long bonds: referee in __float128
-        quad, qoff, _ = O.eri_quad(sh, picks[bad], n_threads=THREADS)
-        full = ref.copy()
-        for k, t in enumerate(bad):
-            full[ref_off[t]:ref_off[t] + sizes[t]] = quad[qoff[k]:qoff[k] + sizes[t]]
-        assert violations(full, ref_off) == [], "quartets outside half a step of the referee"
-    print("molecule sample: %d of %d quartets refereed in __float128" % (len(bad), len(picks)))
+    err, nref = check_quartets(sh, picks, vals, ref, ref_off, ref_sizes, THREADS)
+    oc, oe = O.compress(16, vals, np.append(ref_off, len(vals)))
+    assert np.array_equal(oe, scales)
+    assert np.array_equal(oc, codes)
+    # decoded values within half a step (plus the FP64 bar) of the oracle
+    step = np.repeat(scales, sizes)
+    bmax = np.repeat(scales / cn, sizes)
+    assert np.all(np.abs(codes * step - vals) <= step / 2 + 4 * np.spacing(bmax))
+    print("molecule sample: max |err| %.3e (%d quartets refereed in __float128)" % (err, nref))

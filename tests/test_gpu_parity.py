@@ -1,8 +1,8 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars: FP64 ERIs within 1e-12 Hartree absolute of the oracle (a 1e-14
-relative allowance covers quartets whose values reach O(100) Ha, where the
-oracle's own double rounding is of that order); the fused codes and scales
+Bars: FP64 ERIs within 1e-12 Hartree absolute of the oracle (quartets that
+miss it against the double oracle are refereed by its __float128 build, with
+the same absolute bar); the fused codes and scales
 bit-identical to the oracle's compressor fed the GPU's doubles; decompressed
 values within half a quantisation step."""
 import os
@@ -18,8 +18,6 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 N_PER_CLASS = 67          # ragged against 64-lane and multi-slot workgroups
-ABS_TOL = 1e-12
-REL_TOL = 1e-14
 THREADS = min(16, os.cpu_count() or 1)
 
 
@@ -207,3 +205,59 @@ def test_full_size_sampled():
     oc, oe = O.compress(16, got, blk)
     assert np.array_equal(oe, scales)
     assert np.array_equal(oc, codes)
+
+
+def _scale_blocks(plan):
+    """Value offsets of the plan's scale blocks (G consecutive quartets of a
+    class in plan order; the last block of a class may be shorter)."""
+    G = plan.scale_block
+    off = []
+    for cid in range(256):
+        n = int(plan.class_quartets[cid])
+        if n == 0:
+            continue
+        m = int((plan.class_eri_off[cid + 1] - plan.class_eri_off[cid]) // n)
+        off.append(plan.class_eri_off[cid] + m * np.arange(0, n, G))
+    return np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
+
+
+@pytest.mark.parametrize("case,G", [("ss_k3", 64), ("ss_k3", 1), ("fd_pp", 64), ("fd_pp", 7), ("fd_pp", 1)])
+def test_scale_block(case, G):
+    """Scale blocks of G quartets (eq. 9 over the block): codes and scales
+    bit-identical to the oracle's compressor fed the GPU doubles over the same
+    blocks; decoded values within half a step of the oracle's values; the
+    codes do not depend on whether FP64 values are requested too."""
+    from paper_2303_13632_amd import eri
+    if case == "ss_k3":
+        shells, quartets = W.small_case()
+    else:
+        shells, quartets = W.class_case(W.class_id(3, 2, 1, 1), n_quartets=200)
+    ref, _, sizes = O.eri(shells, quartets, n_threads=THREADS)
+    plan = eri.Plan(shells, quartets, precision="fp64", bits=16, scale_block=G)
+    assert plan.scale_block == G and plan.out_blocks == -(-len(quartets) // G)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    _, c2, s2 = plan.alloc(eri=False, codes=True)
+    plan.compute(None, c2, s2)
+    torch.cuda.synchronize()
+    vals = e.cpu().numpy()[: plan.n_eri]
+    codes = c.cpu().numpy()[: plan.n_eri].astype(np.int32)
+    scales = s.cpu().numpy()[: plan.out_blocks]
+    assert np.array_equal(codes, c2.cpu().numpy()[: plan.n_eri].astype(np.int32))
+    assert np.array_equal(scales, s2.cpu().numpy()[: plan.out_blocks])
+    got = plan.to_user(vals)
+    check_quartets(shells, quartets, got, ref, _blocks(sizes), sizes, THREADS)
+    blk = _scale_blocks(plan)
+    oc, oe = O.compress(16, vals, blk)
+    assert np.array_equal(oe, scales)
+    assert np.array_equal(oc, codes)
+    # decoded (plan order) against the oracle's values in plan order
+    pos, eoff = plan.layout()
+    ref_plan = np.empty(plan.n_eri)
+    for t in range(len(quartets)):
+        ref_plan[eoff[t]:eoff[t] + sizes[t]] = ref[_blocks(sizes)[t]:_blocks(sizes)[t] + sizes[t]]
+    step = np.repeat(scales, np.diff(blk))
+    bmax = step * 32767.0
+    assert np.all(np.abs(codes * step - ref_plan) <= step / 2 + 4 * np.spacing(bmax) + 1e-12)
+    if G == 64 and case == "ss_k3":
+        assert len(np.unique(np.abs(codes))) > 100     # a block resolves the values within it

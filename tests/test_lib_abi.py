@@ -86,10 +86,59 @@ def test_kernel_tag_suffixes_match_generator():
     spec.loader.exec_module(G)
     tags = {v: k for k, v in vars(G).items() if k.startswith("TAG_") and isinstance(v, int)}
     assert set(tags) == set(eri.KERNEL_TAG_SUFFIX)
-    # generated names: default, half-register, two-wavefront forms of [ff|fp]
-    cp = G.ClassPlan(3, 3, 3, 1)
+    # generated names: default, half-register and alternate forms of [ff|df]
+    cp = G.ClassPlan(3, 3, 2, 3)
     name = G.kernel_name("fp64", cp.user)
     assert G.emit_class(cp, "fp64", occupancy=2)[0] == name + eri.KERNEL_TAG_SUFFIX[G.TAG_OCC2]
-    assert G.emit_class(G.ClassPlan(3, 3, 3, 1), "fp64", alt=True)[0] == \
+    assert G.emit_class(G.ClassPlan(3, 3, 2, 3), "fp64", alt=True)[0] == \
         G.kernel_name("fp64", cp.user, True)
     assert G.kernel_name("fp64", cp.user, True) == name + eri.KERNEL_TAG_SUFFIX[G.TAG_ALT]
+
+
+@pytest.mark.parametrize("bits", [3, 7, 12, 16, 20, 32])
+def test_host_unpack_and_decompress_against_oracle(bits):
+    """eri_unpack_host / eri_decompress_host (host memory, no GPU): the packed
+    stream the oracle writes decodes to the oracle's codes and to the
+    oracle's decompressed values, bit for bit; ragged and empty blocks."""
+    import oracle as O
+    rng = np.random.default_rng(bits)
+    sizes = rng.integers(0, 300, size=97)
+    sizes[5] = 0
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    x = rng.standard_normal(off[-1]) * np.repeat(10.0 ** rng.uniform(-8, 1, size=len(sizes)), sizes)
+    codes, eps = O.compress(bits, x, off)
+    packed, woff = O.pack(bits, codes, off)
+    ref = O.decompress(codes, eps, off)
+    c, v = eri.unpack_host(bits, packed, off, woff, scales=eps, codes=True, values=True, n_threads=3)
+    assert np.array_equal(c, codes)
+    assert np.array_equal(v, ref)
+    ct = codes.astype(np.int8 if bits <= 8 else np.int16 if bits <= 16 else np.int32)
+    assert np.array_equal(eri.decompress_host(bits, ct, eps, off, n_threads=2), ref)
+
+
+def test_host_decompress_rejects_bad_arguments():
+    lib = eri.load()
+    assert lib.eri_decompress_host(1, None, None, 0, None, None, 0) == eri.ERI_EUNSUPPORTED
+    assert lib.eri_decompress_host(16, None, None, 2, None, None, 0) == eri.ERI_EINVAL
+    assert lib.eri_unpack_host(40, None, 0, None, None, None, None, None, 0) == eri.ERI_EUNSUPPORTED
+    assert lib.eri_unpack_host(12, None, 2, None, None, None, None, None, 0) == eri.ERI_EINVAL
+    assert lib.eri_plan_set_geometry(None, None, None) == eri.ERI_EINVAL
+
+
+def test_generator_refuses_unsafe_half_register_form():
+    """The generator raises (instead of silently skipping) for the kernel form
+    that returned wrong values on the GPU: two bra indices per lane at half
+    the registers with HRR staging in more chunks than the 32 KB form."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(eri.__file__), "csrc", "codegen.py")
+    spec = importlib.util.spec_from_file_location("eri_codegen2", path)
+    G = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(G)
+    ff = G.ClassPlan(3, 3, 3, 3)
+    assert G.unsafe_half_register(ff, 16384) and not G.occupancy_variant(ff)
+    with pytest.raises(ValueError):
+        G.emit_class(ff, "fp64", occupancy=2)
+    # single-subslot classes keep their half-register forms, also with 3 chunks
+    fdf = G.ClassPlan(3, 3, 2, 3)
+    assert G.lds_chunks(fdf, 16384) == 3 and G.occupancy_variant(fdf)
