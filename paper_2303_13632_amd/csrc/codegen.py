@@ -518,10 +518,15 @@ def emit_store_T(em, cp, outs):
 # Mode W kernel
 # ---------------------------------------------------------------------------
 def wave_layout(cp):
-    """Lanes per slot, subslot lists of bra indices e."""
+    """Lanes per slot, subslot lists of bra indices e.  With one subslot the
+    indices are laid out in x-columns (fixed e_y, e_z; e_x = 0, 1, ...), so
+    that e - 1_x is always the lane below e: the ket recurrence's coupling
+    term along x then moves between lanes by a DPP shift instead of an LDS
+    permute."""
     all_e = [e for L in range(cp.Lab + 1) for e in comps(L)]
     if len(all_e) <= 64:
-        subs = [all_e]
+        subs = [[(ex, ey, ez) for ey in range(cp.Lab + 1) for ez in range(cp.Lab + 1 - ey)
+                 for ex in range(cp.Lab + 1 - ey - ez)]]
     else:
         subs = [[e for e in all_e if sum(e) % 2 == 0], [e for e in all_e if sum(e) % 2 == 1]]
     ep = max(len(s) for s in subs)
@@ -713,7 +718,11 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
                 if fp[i] >= 1:
                     fpp = vsub(fp, UNIT[i])
                     expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), V[(s, fpp, m)], V[(s, fpp, m + 1)])
-                expr += " + ce%s%d * __shfl(%s, s%s%d)" % (ax, s, V[(ss, fp, m + 1)], ax, s)
+                if S == 1 and ax == "x":
+                    # e - 1_x is the lane below (x-column layout)
+                    expr += " + cex0 * eri_lane_below(%s)" % V[(ss, fp, m + 1)]
+                else:
+                    expr += " + ce%s%d * __shfl(%s, s%s%d)" % (ax, s, V[(ss, fp, m + 1)], ax, s)
                 em("const %s %s = %s;" % (real, nm, expr))
                 V[(s, f, m)] = nm
         if f in tset:

@@ -79,6 +79,23 @@ ERI_DEV void eri_pq_setup(const eri_prim_pair& B, const eri_prim_pair& K, eri_pq
 }
 
 // ---------------------------------------------------------------------------
+// Value held by lane - 1 of the wavefront (lane 0 gets 0): a DPP wave shift
+// right by one lane, executed by the vector ALU without LDS traffic.  Slot
+// kernels lay their bra indices out so that e - 1_x sits one lane below e.
+// ---------------------------------------------------------------------------
+ERI_DEV double eri_lane_below(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+ERI_DEV float eri_lane_below(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+
+// ---------------------------------------------------------------------------
 // Quantiser of the fused compression: eps = b_max * c_n, inv = 1/eps,
 // q = round-half-away(x * inv) clamped to +-qmax; eps == 0 gives q = 0; a
 // subnormal eps whose reciprocal overflows is handled by dividing, x / eps.
