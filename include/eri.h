@@ -172,6 +172,24 @@ int eri_plan_quartets(const eri_plan* plan, int32_t class_id, int64_t first, int
  * set) and replayed as a single graph launch. */
 int eri_compute(eri_plan* plan, void* stream, double* out_eri, void* out_codes, double* out_scales);
 
+/* eri_compute for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * it calls no hipMalloc, hipFree or allocating library routine and builds no
+ * graph; every class launch is made on `stream` in turn.  Same outputs,
+ * bit for bit, as eri_compute.  ERI_PLAN_ALL_QUARTETS plans expand each
+ * launch chunk's quartet items into a static device array of
+ * ERI_NOALLOC_MAX_ITEMS items (32 MiB, one copy per GPU the library runs on,
+ * held until the process ends) instead of the plan's item buffer; such a
+ * plan must have been created with chunk_quartets <= ERI_NOALLOC_MAX_ITEMS
+ * (ERI_EUNSUPPORTED otherwise: a class chunk larger than the array).
+ * Explicit plans use no scratch.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads) race,
+ * and the array keeps the last call's items.  Devices with ordinals beyond
+ * ERI_NOALLOC_MAX_DEVICES - 1 return ERI_EUNSUPPORTED. */
+#define ERI_NOALLOC_MAX_ITEMS ((int64_t)1 << 22)
+#define ERI_NOALLOC_MAX_DEVICES 64
+int eri_compute_noalloc(eri_plan* plan, void* stream, double* out_eri, void* out_codes, double* out_scales);
+
 /* Same as eri_compute for the quartets of one class only (class id
  * La*64+Lb*16+Lc*4+Ld); pointers address the whole plan-order arrays. */
 int eri_compute_class(eri_plan* plan, int32_t class_id, void* stream, double* out_eri,

@@ -840,6 +840,49 @@ extern "C" int eri_compute(eri_plan* p, void* stream, double* out_eri, void* out
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Entry point that allocates nothing: the expanded quartet items of a
+// screened plan's launch chunk go to a file-scope device array instead of
+// the plan's item buffer, and the launches are made one by one (no graph).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) eri_item scratch[ERI_NOALLOC_MAX_ITEMS];
+
+static std::mutex g_scratch_mu;
+static eri_item* g_scratch_dev[ERI_NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the current device (looked up once per
+// device; each device holds its own copy at its own address).
+static int scratch_items(int dev, eri_item** out)
+{
+    if (dev < 0 || dev >= ERI_NOALLOC_MAX_DEVICES) return ERI_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        ERI_HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = (eri_item*)ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return ERI_OK;
+}
+
+extern "C" int eri_compute_noalloc(eri_plan* p, void* stream, double* out_eri, void* out_codes, double* out_scales)
+{
+    int rc = compute_check(p, out_eri, out_codes, out_scales);
+    if (rc) return rc;
+    if (p->batched)
+        for (const auto& bc : p->bclass)
+            if (bc.chunk > ERI_NOALLOC_MAX_ITEMS) return ERI_EUNSUPPORTED;
+    int cur = 0;
+    ERI_HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) ERI_HIP_TRY(hipSetDevice(p->device));
+    eri_item* items = nullptr;
+    if (p->batched) rc = scratch_items(p->device, &items);
+    for (int c = 0; c < 256 && rc == ERI_OK; ++c)
+        rc = launch_class(p, c, (hipStream_t)stream, out_eri, out_codes, out_scales, items);
+    if (cur != p->device) (void)hipSetDevice(cur);
+    return rc;
+}
+
 extern "C" int eri_compute_class(eri_plan* p, int32_t c, void* stream, double* out_eri, void* out_codes,
                                  double* out_scales)
 {

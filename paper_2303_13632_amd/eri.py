@@ -84,6 +84,7 @@ def load():
     lib.eri_plan_quartets.argtypes = [_vp, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, _i32p]
     lib.eri_compute.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.eri_compute_class.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, _vp]
+    lib.eri_compute_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp]
     lib.eri_compress.argtypes = [ctypes.c_int32, _vp, ctypes.c_int64, _vp, _vp, _vp, _vp]
     lib.eri_decompress.argtypes = [ctypes.c_int32, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
     lib.eri_backward.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp, _vp, _vp]
@@ -265,6 +266,11 @@ class Plan:
     def compute(self, out_eri=None, out_codes=None, out_scales=None, stream=None):
         _check(load().eri_compute(self._h, _stream(stream), _ptr(out_eri), _ptr(out_codes), _ptr(out_scales)),
                "eri_compute")
+
+    def compute_noalloc(self, out_eri=None, out_codes=None, out_scales=None, stream=None):
+        """eri_compute_noalloc: the same outputs with no device allocation (static scratch)."""
+        _check(load().eri_compute_noalloc(self._h, _stream(stream), _ptr(out_eri), _ptr(out_codes), _ptr(out_scales)),
+               "eri_compute_noalloc")
 
     def compute_class(self, cid, out_eri=None, out_codes=None, out_scales=None, stream=None):
         _check(load().eri_compute_class(self._h, int(cid), _stream(stream), _ptr(out_eri), _ptr(out_codes),
