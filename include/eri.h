@@ -109,7 +109,8 @@ typedef struct {
                                      (name suffix _a), 2 half-register slots (suffix _o2),
                                      3 two-wavefront slots (suffix _w2), 4 bra and ket exchanged
                                      (suffix _s), 5 two-wavefront slots at half the registers
-                                     (suffix _w2o2) */
+                                     (suffix _w2o2), 6 two-wavefront slots split by x-columns
+                                     (suffix _w2x) */
     int32_t class_fp32[256];      /* 1: the class's recurrences run in FP32 (FP32-mixed plans, classes
                                      whose FP32 error was measured within 1e-8 Ha); 0: FP64 */
     int32_t scale_block;          /* G of eri_plan_opts (1 = per quartet) */

@@ -821,21 +821,46 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     return name, em.text()
 
 
-def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
-    """Two-subslot classes (|e| <= 6, 84 bra indices) on two wavefronts: wave
-    w holds the bra indices of parity w, one per lane, so a lane carries one
-    set of accumulators instead of two.  The ket VRR's coupling term comes
-    from the other parity, i.e. the other wave: each ket level's values are
-    exchanged through LDS, with a barrier before and after each level's
-    reads.  Primitive quartets are staged 64 at a time by the first wave.
-    One LDS pool holds the staging and the exchange during the recurrences,
-    then the HRR staging, so two workgroups fit on a CU."""
+def xcolumn_waves(cp):
+    """The bra indices of an f-f bra (|e| <= 6: 84) split over two
+    wavefronts by whole x-columns (fixed e_y, e_z; e_x ascending on
+    consecutive lanes), longest columns first, each to the emptier wave."""
+    cols = [[(ex, ey, ez) for ex in range(cp.Lab + 1 - ey - ez)]
+            for ey in range(cp.Lab + 1) for ez in range(cp.Lab + 1 - ey)]
+    cols.sort(key=lambda col: -len(col))
+    waves = [[], []]
+    for col in cols:
+        w = 0 if len(waves[0]) <= len(waves[1]) else 1
+        waves[w] += col
+    assert max(len(w) for w in waves) <= 64
+    return waves
+
+
+def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
+    """Two-subslot classes (|e| <= 6, 84 bra indices) on two wavefronts, one
+    bra index per lane, so a lane carries one set of accumulators instead of
+    two.  Primitive quartets are staged 64 at a time by the first wave.  One
+    LDS pool holds the staging and the exchange during the recurrences, then
+    the HRR staging, so two workgroups fit on a CU.
+
+    layout "parity": wave w holds the bra indices of parity w, so the ket
+    VRR's coupling term e_i/(2(p+q)) [e-1_i 0|f-1_i 0] always comes from the
+    other wave: each ket level's values are exchanged through LDS, with a
+    barrier before and after each level's reads.
+    layout "xcol": the waves hold whole x-columns (xcolumn_waves), so the
+    coupling along x comes from the lane below in the same wave (a DPP
+    shift); only the y and z couplings, which lower f along y or z and so
+    need values with f_x = 0, go through LDS, into one of two exchange
+    buffers used in turn, one barrier per level."""
     real = REALS[prec]
     mixed = prec == "mixed"
+    xcol = layout == "xcol"
     em = Emitter()
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     subs, EP = wave_layout(cp)
     assert len(subs) == 2
+    if xcol:
+        subs = xcolumn_waves(cp)
     E_T = cp.E_T
     tgt_index = {e: k for k, e in enumerate(E_T)}
     NTE = len(E_T)
@@ -849,36 +874,51 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
     NCH = (NCD + CH - 1) // CH
     Lcd = cp.Lcd
     # per wave and lane: ex, ey, ez, valid, tgt, src_x, src_y, src_z (src: lane of
-    # e - 1_i in the other wave)
+    # e - 1_i in the other wave; xcol: flat index 64 w + lane in either wave)
     rows = []
+    where = {e: (w, ls) for w in range(2) for ls, e in enumerate(subs[w])}
     for w in range(2):
         other = subs[1 - w]
         for ls in range(64):
             if ls < len(subs[w]):
                 e = subs[w][ls]
-                src = [other.index(vsub(e, UNIT[i])) if e[i] >= 1 else ls for i in range(3)]
+                if xcol:
+                    src = []
+                    for i in range(3):
+                        if e[i] >= 1:
+                            w2, l2 = where[vsub(e, UNIT[i])]
+                            if i == 0:
+                                assert w2 == w and l2 == ls - 1
+                            src.append(64 * w2 + l2)
+                        else:
+                            src.append(64 * w + ls)
+                else:
+                    src = [other.index(vsub(e, UNIT[i])) if e[i] >= 1 else ls for i in range(3)]
                 rows.append([e[0], e[1], e[2], 1, tgt_index.get(e, -1)] + src)
             else:
-                rows.append([0, 0, 0, 0, -1, ls, ls, ls])
+                rows.append([0, 0, 0, 0, -1, ls, ls, ls] if not xcol else [0, 0, 0, 0, -1] + [64 * w + ls] * 3)
     tbl = "eri_tbl_" + name[4:]
     em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], mode W on two waves (%d + %d lanes), %s"
        % (cp.user + (cp.perm, a, b, c, d, len(subs[0]), len(subs[1]), prec)))
-    em("static __constant__ signed char %s[128][8] = {" % tbl)
+    em("static __constant__ signed char %s[128][8] = {" % tbl)   # lane sources 0..127 fit
     for row in rows:
         em("  {" + ", ".join(str(v) for v in row) + "},")
     em("};")
     # exchange slots of one level: values (f, m) with |f| = L - 1, 1 <= m <= Lcd - L + 1
+    # (xcol: only f with f_x = 0, the ones the y and z couplings read)
     xidx = {}
     NX = 1
     for L in range(1, Lcd + 1):
         k = 0
         for fp in comps(L - 1):
+            if xcol and fp[0] > 0:
+                continue
             for m in range(1, Lcd - L + 2):
                 xidx[(L, fp, m)] = k
                 k += 1
         NX = max(NX, k)
     NF = cp.Ltot + 1 + 17
-    NSU = max(NTE * CH, NF * 64 + 2 * NX * 64)
+    NSU = max(NTE * CH, NF * 64 + 2 * NX * 64 * (2 if xcol else 1))
     if waves > 1:
         # `waves` workgroups per CU's SIMD pair: the register budget halves
         em("__global__ __launch_bounds__(128, %d) void %s(eri_class_args A)" % (waves, name))
@@ -886,8 +926,13 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
         em("__global__ __launch_bounds__(128) void %s(eri_class_args A)" % name)
     em.block("")
     em("__shared__ double s_u[%d];" % NSU)
-    em("double (*s_x)[%d][64] = reinterpret_cast<double (*)[%d][64]>(s_u + %d);   // [wave][value][lane]"
-       % (NX, NX, NF * 64))
+    if xcol:
+        em("double (*s_x)[%d][128] = reinterpret_cast<double (*)[%d][128]>(s_u + %d);   // [buffer][value][64 wave + lane]"
+           % (NX, NX, NF * 64))
+        em("int xb = 0;   // exchange buffer of the current ket level (uniform)")
+    else:
+        em("double (*s_x)[%d][64] = reinterpret_cast<double (*)[%d][64]>(s_u + %d);   // [wave][value][lane]"
+           % (NX, NX, NF * 64))
     em("__shared__ double s_red[128];")
     em("double (*s_t)[%d] = reinterpret_cast<double (*)[%d]>(s_u);" % (CH, CH))
     em("const int tid = threadIdx.x;")
@@ -974,11 +1019,23 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
         em("%s += %s;" % (acc[ZERO], ("(double)" + V[(ZERO, 0)]) if mixed else V[(ZERO, 0)]))
     nvar = 0
     for L in range(1, Lcd + 1):
-        em("__syncthreads();   // the other wave has read the previous exchange")
-        for fp in comps(L - 1):
-            for m in range(1, Lcd - L + 2):
-                em("s_x[wv][%d][ls] = (double)%s;" % (xidx[(L, fp, m)], V[(fp, m)]))
-        em("__syncthreads();")
+        if xcol:
+            # buffers alternate level by level (and across primitive quartets):
+            # a wave past this level's barrier has seen the other finish
+            # reading the buffer it is about to write
+            em("xb ^= 1;")
+            for fp in comps(L - 1):
+                if fp[0] > 0:
+                    continue
+                for m in range(1, Lcd - L + 2):
+                    em("s_x[xb][%d][tid] = (double)%s;" % (xidx[(L, fp, m)], V[(fp, m)]))
+            em("__syncthreads();")
+        else:
+            em("__syncthreads();   // the other wave has read the previous exchange")
+            for fp in comps(L - 1):
+                for m in range(1, Lcd - L + 2):
+                    em("s_x[wv][%d][ls] = (double)%s;" % (xidx[(L, fp, m)], V[(fp, m)]))
+            em("__syncthreads();")
         for f in comps(L):
             i = 0 if f[0] > 0 else (1 if f[1] > 0 else 2)
             ax = "xyz"[i]
@@ -990,7 +1047,12 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1):
                 if fp[i] >= 1:
                     fpp = vsub(fp, UNIT[i])
                     expr += " + (%s * hq) * (%s - rq * %s)" % (lit(fp[i]), V[(fpp, m)], V[(fpp, m + 1)])
-                expr += " + ce%s0 * (%s)s_x[wv ^ 1][%d][s%s0]" % (ax, real, xidx[(L, fp, m + 1)], ax)
+                if xcol and i == 0:
+                    expr += " + cex0 * eri_lane_below(%s)" % V[(fp, m + 1)]
+                elif xcol:
+                    expr += " + ce%s0 * (%s)s_x[xb][%d][s%s0]" % (ax, real, xidx[(L, fp, m + 1)], ax)
+                else:
+                    expr += " + ce%s0 * (%s)s_x[wv ^ 1][%d][s%s0]" % (ax, real, xidx[(L, fp, m + 1)], ax)
                 em("const %s %s = %s;" % (real, nm, expr))
                 V[(f, m)] = nm
             if f in tset:
@@ -1156,6 +1218,7 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 # kernel tags (last field of eri_kernel_info): which generated kernel a variant launches
 TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES, TAG_SWAP = 0, 1, 2, 3, 4
 TAG_TWO_WAVES_OCC2 = 5
+TAG_TWO_WAVES_XCOL = 6
 
 
 def two_wave_form(cp):
@@ -1266,6 +1329,8 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                     # larger ket, or with bra and ket exchanged, it never beat the others
                     parts.append(emit_mode_W2(cp, prec, wname + "o2", waves=2)[1])
                     infos.append(w2_info(cp, wname + "o2", TAG_TWO_WAVES_OCC2))
+                parts.append(emit_mode_W2(cp, prec, wname + "x", layout="xcol")[1])
+                infos.append(w2_info(cp, wname + "x", TAG_TWO_WAVES_XCOL))
             assert len(infos) <= MAXVAR, (user, len(infos))
             for k, info in enumerate(infos):
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info[:-1] + fp32))

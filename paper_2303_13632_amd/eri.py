@@ -364,7 +364,7 @@ class Plan:
 
 
 # Name suffix of the generated kernel of each variant tag (eri_plan_info.class_tag)
-KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2"}
+KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2", 6: "_w2x"}
 
 
 def _ncart(L):
