@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--bits", type=int, default=16)
+    ap.add_argument("--packed", action="store_true",
+                    help="codes as the packed 512-bit word stream written by the kernels (ERI_PLAN_PACKED)")
     ap.add_argument("--quartets-per-class", type=int, default=65536)
     ap.add_argument("--classes", default="all", help="'all' or comma-separated class ids")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -182,52 +184,55 @@ def measured_traffic(kernel):
 
 
 def bench_packed(args, classes, bits):
-    """The 256-class workload with n-bit codes (int16 containers from the
-    fused kernels) packed into the 512-bit word stream; a step is every class
-    launch plus the pack kernel, timed by HIP events on the launch stream."""
+    """The 256-class workload with n-bit codes written by the ERI kernels as the
+    packed stream of 512-bit words (ERI_PLAN_PACKED: each quartet's codes
+    staged in LDS and packed in the same kernel), timed like the headline;
+    then eq. 11 on the host: a bounded prefix of the stream (whole quartets)
+    copied to host memory and decompressed by eri_unpack_host on every host
+    thread."""
     import torch
     from paper_2303_13632_amd import eri
     shells, quartets = build_workload(args.quartets_per_class, classes)
-    plan = eri.Plan(shells, quartets, precision="fp64", bits=bits, device=0)
+    plan = eri.Plan(shells, quartets, precision="fp64", bits=bits, device=0, packed=True)
     del shells, quartets
     if not args.no_tune:
         plan.tune(sample_quartets=args.quartets_per_class, trials=2, cache=args.tune_cache or None)
-    _, codes, scales = plan.alloc(eri=False, codes=True)
+    _, words, scales = plan.alloc(eri=False, codes=True)
+    stream = torch.cuda.current_stream()
+    plan.compute(None, words, scales, stream=stream)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.compute(None, words, scales, stream=stream)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res = {"value": plan.n_eri / (ms / 1e3) / 1e9, "unit": "GERIS", "bits": bits, "ms_per_step": ms,
+           "packed_bytes": int(plan.class_word_off[256]) * 64, "int16_container_bytes": int(plan.n_eri) * 2,
+           "note": "same workload; the ERI kernels write the packed stream themselves (floor(512/n) codes per "
+                   "512-bit word, every quartet word-aligned), no container array and no second pass"}
+    # host decompression of a prefix of whole quartets (about 2 GB of words)
     off = []
     for c in range(256):
         n = int(plan.class_quartets[c])
         if n:
             m = int((plan.class_eri_off[c + 1] - plan.class_eri_off[c]) // n)
-            off.append(plan.class_eri_off[c] + m * np.arange(n, dtype=np.int64))
+            off.append(plan.class_eri_off[c] + m * np.arange(n))
     off = np.concatenate(off + [np.array([plan.n_eri], dtype=np.int64)])
     woff = eri.packed_word_offsets(bits, off)
-    d_off = torch.tensor(off, device="cuda")
-    d_woff = torch.tensor(woff, device="cuda")
-    packed = torch.empty(8 * int(woff[-1]), dtype=torch.int64, device="cuda")
-    stream = torch.cuda.current_stream()
-    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    plan.compute(None, codes, scales, stream=stream)
-    eri.pack(bits, codes, d_off, d_woff, packed, stream=stream)
-    torch.cuda.synchronize()
-    steps = max(1, args.steps // 2)
-    comp = pack_ms = 0.0
-    for _ in range(steps):
-        e0.record(stream)
-        plan.compute(None, codes, scales, stream=stream)
-        e1.record(stream)
-        eri.pack(bits, codes, d_off, d_woff, packed, stream=stream)
-        e2.record(stream)
-        torch.cuda.synchronize()
-        comp += e0.elapsed_time(e1)
-        pack_ms += e1.elapsed_time(e2)
-    comp /= steps
-    pack_ms /= steps
-    res = {"value": plan.n_eri / ((comp + pack_ms) / 1e3) / 1e9, "unit": "GERIS", "bits": bits,
-           "ms_per_step": comp + pack_ms, "pack_ms": pack_ms,
-           "packed_bytes": int(woff[-1]) * 64, "int16_container_bytes": int(plan.n_eri) * 2,
-           "note": "same workload; codes computed into int16 containers, then packed into 512-bit words of "
-                   "floor(512/n) codes with every quartet word-aligned"}
-    del codes, scales, packed
+    nq = int(np.searchsorted(woff, (2 << 30) // 64, side="right")) - 1
+    nw = int(woff[nq])
+    host_words = words[: 8 * nw].cpu().numpy()
+    host_scales = scales[:nq].cpu().numpy()
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    _, vals = eri.unpack_host(bits, host_words, off[: nq + 1], woff[: nq + 1], scales=host_scales, codes=False,
+                              values=True, n_threads=threads)
+    th = time.perf_counter() - t0
+    res["host_decompress"] = {"value": float(off[nq]) / th / 1e9, "unit": "GERIS", "threads": threads,
+                              "sample": "first %d quartets (%d ERIs, %.2f GB of packed words) to FP64" %
+                                        (nq, int(off[nq]), nw * 64 / 1e9)}
+    del vals, host_words, words, scales
     plan.close()
     torch.cuda.empty_cache()
     return res
@@ -243,7 +248,8 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
     shells, quartets = build_workload(args.quartets_per_class, classes)
     log("workload: %d quartets, %d shells (%.1fs)" % (len(quartets), len(shells["L"]), time.time() - t0))
     t0 = time.time()
-    plan = eri.Plan(shells, quartets, precision=precision, bits=bits, device=0)
+    packed = bool(getattr(args, "packed", False)) and bits > 0
+    plan = eri.Plan(shells, quartets, precision=precision, bits=bits, device=0, packed=packed)
     del shells, quartets
     log("plan %s: %d ERIs, %d primitive quartets, %.1f GB on device (%.1fs)"
         % (precision, plan.n_eri, plan.n_prim_quartets, plan.device_bytes / 1e9, time.time() - t0))
@@ -308,7 +314,8 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
     config = {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
                           "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, %s"
                           % (len(active), args.quartets_per_class, precision,
-                             "int%d per-quartet compression" % bits if bits else "FP64 output, no compression"),
+                             ("int%d per-quartet compression" % bits + (", codes packed in 512-bit words" if packed else ""))
+                             if bits else "FP64 output, no compression"),
               "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
               "n_prim_quartets": int(plan.n_prim_quartets), "precision": precision, "bits": bits}
     res = {"geris": geris, "ms_per_step": ms_step, "config": config, "roofline": roof,

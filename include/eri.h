@@ -66,12 +66,13 @@ extern "C" {
 typedef struct eri_plan eri_plan;
 
 #define ERI_PLAN_ALL_QUARTETS 1  /* plan every unique Schwarz-screened quartet of the shell set */
+#define ERI_PLAN_PACKED 2        /* codes written as the packed 512-bit word stream (see eri_compute) */
 
 typedef struct {
     int32_t precision;          /* ERI_FP64 or ERI_FP32_MIXED */
     int32_t bits;               /* code width n of eq. 10: 0 = no codes, else 2..32 */
     int32_t device;             /* HIP device ordinal */
-    int32_t flags;              /* ERI_PLAN_ALL_QUARTETS or 0 */
+    int32_t flags;              /* ERI_PLAN_ALL_QUARTETS and/or ERI_PLAN_PACKED, or 0 */
     double schwarz_threshold;   /* with ERI_PLAN_ALL_QUARTETS: keep (ab|cd) with Q_ab Q_cd >= this */
     int64_t ring_bytes;         /* with ERI_PLAN_ALL_QUARTETS: bound on the output held (0 = all) */
     int64_t chunk_quartets;     /* with ERI_PLAN_ALL_QUARTETS: quartets per launch chunk (0 = 2^25);
@@ -110,13 +111,16 @@ typedef struct {
                                      3 two-wavefront slots (suffix _w2), 4 bra and ket exchanged
                                      (suffix _s), 5 two-wavefront slots at half the registers
                                      (suffix _w2o2), 6 two-wavefront slots split by x-columns
-                                     (suffix _w2x) */
+                                     at half the registers (suffix _w2xo2); the default of a
+                                     class with an f-f bra is the two-wavefront x-column kernel */
     int32_t class_fp32[256];      /* 1: the class's recurrences run in FP32 (FP32-mixed plans, classes
                                      whose FP32 error was measured within 1e-8 Ha); 0: FP64 */
     int32_t scale_block;          /* G of eri_plan_opts (1 = per quartet) */
     int32_t reserved2;
     int64_t class_scale_off[257]; /* first scale of each class: class c holds
                                      ceil(class_ring[c] / G) scales */
+    int64_t class_word_off[257];  /* ERI_PLAN_PACKED: first 64-byte word of each class; a quartet of
+                                     class c holds ceil(n_ERIQ / floor(512 / bits)) words */
 } eri_plan_info;
 
 /* Build a plan over the quartets of a shell set (eq. 3 inputs).  Computes on
@@ -133,8 +137,9 @@ typedef struct {
  * j of class c lands in slot j mod class_ring[c]); opts->ring_bytes bounds the
  * total (codes, or FP64 values when bits = 0).
  * Returns ERI_EINVAL for null pointers or indices outside [0, n_shells),
- * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K], a bad `bits`, or
- * scale_block > 1 with ERI_PLAN_ALL_QUARTETS,
+ * ERI_EUNSUPPORTED for L > 3, K outside [1, ERI_MAX_K], a bad `bits`,
+ * scale_block > 1 with ERI_PLAN_ALL_QUARTETS or ERI_PLAN_PACKED, or
+ * ERI_PLAN_PACKED with bits = 0,
  * ERI_ENOMEM / ERI_EHIP on allocation or upload failure.  On success *out owns
  * all device memory of the plan until eri_plan_destroy(). */
 int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* L, const int32_t* K,
@@ -168,6 +173,14 @@ int eri_plan_quartets(const eri_plan* plan, int32_t class_id, int64_t first, int
  * several workgroups, so the class's FP64 values are written first (to
  * out_eri, or to a staging buffer the plan holds) and a second kernel
  * compresses each block.
+ * With ERI_PLAN_PACKED, out_codes receives instead the packed stream of the
+ * paper's output words (Sec. III-B; the layout of eri_pack with one block
+ * per quartet in plan order): class c starts at word class_word_off[c], each
+ * quartet occupies ceil(n_ERIQ / floor(512/n)) 64-byte words, its code k in
+ * word k / floor(512/n) at bits (k mod floor(512/n)) * n as its n low
+ * two's-complement bits, unused bits zero.  The kernels stage each quartet's
+ * codes in LDS and write its words themselves (no container array, no
+ * second pass); out_codes holds class_word_off[256] * 64 bytes.
  * Returns ERI_EINVAL if no output is requested.  For ERI_PLAN_ALL_QUARTETS
  * plans all launches are captured once into a hipGraph (per output pointer
  * set) and replayed as a single graph launch. */

@@ -120,6 +120,49 @@ ERI_DEV int eri_quantize_mul(double x, double inv, double qmax)
     return (int)fmin(fmax(y, -qmax), qmax);
 }
 
+// ---------------------------------------------------------------------------
+// Packed code stream written by the kernels themselves (Sec. III-B: 512-bit
+// output words of floor(512/n) n-bit codes, every quartet starting on a new
+// word).  A quartet's codes are first staged in LDS (int16 for n <= 16, else
+// int32; dynamic shared memory sized at launch), then packed: 64-bit lane q
+// of word w holds the n low bits of codes w*per + k whose bits overlap
+// [64 q, 64 q + 64), code k at bit k*n of the word.
+// ---------------------------------------------------------------------------
+extern __shared__ __align__(16) unsigned char eri_pack_lds[];
+
+ERI_DEV void eri_stage_code(int idx, int wide, int q)
+{
+    if (wide)
+        reinterpret_cast<int32_t*>(eri_pack_lds)[idx] = q;
+    else
+        reinterpret_cast<int16_t*>(eri_pack_lds)[idx] = (int16_t)q;
+}
+
+// Packs the n codes staged at eri_pack_lds[(first code) off, stride] into
+// 8 * wpq 64-bit lanes of `out`, lanes lane, lane + nlanes, ...
+ERI_DEV void eri_pack_words(int n, int off, int stride, int bits, int per, int64_t wpq, uint64_t* __restrict__ out,
+                            int lane, int nlanes)
+{
+    const int wide = bits > 16;
+    const uint64_t mask = (1ull << bits) - 1ull;   // bits <= 32
+    for (int64_t u = lane; u < 8 * wpq; u += nlanes) {
+        const int w = (int)(u >> 3), q8 = (int)(u & 7);
+        const int first = w * per;
+        const int k0 = (64 * q8) / bits;
+        const int k1 = min(per - 1, (64 * q8 + 63) / bits);
+        uint64_t v = 0;
+        for (int k = k0; k <= k1 && first + k < n; ++k) {
+            const int idx = (first + k) * stride + off;
+            const int c = wide ? reinterpret_cast<const int32_t*>(eri_pack_lds)[idx]
+                               : (int)reinterpret_cast<const int16_t*>(eri_pack_lds)[idx];
+            const uint64_t f = (uint64_t)(int64_t)c & mask;
+            const int sh = k * bits - 64 * q8;   // in (-bits, 64)
+            v |= sh >= 0 ? (f << sh) : (f >> -sh);
+        }
+        out[u] = v;
+    }
+}
+
 ERI_DEV void eri_store_code(void* codes, int64_t idx, int bytes, int q)
 {
     if (bytes == 2)

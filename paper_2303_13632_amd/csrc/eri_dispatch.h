@@ -13,7 +13,8 @@ struct eri_kernel_info {
     int32_t perm;        // computed shell k is user shell (perm >> 2k) & 3
     int32_t tag;         // generated kernel: 0 default, 1 alternate mapping, 2 half-register (2 waves/SIMD),
                          // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged, 5 two wavefronts
-                         // at half the registers, 6 two wavefronts split by x-columns
+                         // at half the registers, 6 two wavefronts split by x-columns at half the
+                         // registers (the default of an f-f bra is the two-wavefront x-column form)
     int32_t fp32;        // 1: VRR/HRR in FP32 (FP32-mixed kernel); 0: FP64
 };
 

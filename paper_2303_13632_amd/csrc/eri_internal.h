@@ -145,6 +145,8 @@ struct eri_plan {
     int64_t chunk_cap = 0;
     int64_t pass_cap = 0;               // opts->chunk_quartets: bound on an adjoint pass (0 = default)
     int32_t scale_block = 1;            // quartets per scale block
+    bool packed = false;                // codes written as the packed word stream
+    int64_t class_woff[257] = {};       // packed: first 64-byte word of each class
     int64_t class_soff[257] = {};       // first scale of each class
     double* d_stage = nullptr;          // scale_block > 1: FP64 values of one class (when out_eri is NULL)
     double schwarz = 0.0;

@@ -495,7 +495,9 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
         opts->scale_block < 0)
         return ERI_EINVAL;
     const bool batched = (opts->flags & ERI_PLAN_ALL_QUARTETS) != 0;
-    if (batched && opts->scale_block > 1) return ERI_EUNSUPPORTED;
+    const bool packed = (opts->flags & ERI_PLAN_PACKED) != 0;
+    if ((batched || packed) && opts->scale_block > 1) return ERI_EUNSUPPORTED;
+    if (packed && opts->bits == 0) return ERI_EUNSUPPORTED;
     if (batched) {
         if (quartets || n_quartets) return ERI_EINVAL;
     } else {
@@ -511,6 +513,7 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     p->code_bytes = opts->bits == 0 ? 0 : opts->bits <= 8 ? 1 : opts->bits <= 16 ? 2 : 4;
     p->pass_cap = opts->chunk_quartets;
     p->scale_block = std::max(1, opts->scale_block);
+    p->packed = packed;
     if (opts->bits) {
         p->qmax = (double)((((int64_t)1) << (opts->bits - 1)) - 1);
         p->cn = 1.0 / p->qmax;
@@ -542,6 +545,13 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
             stage = std::max(stage, p->class_eoff[c + 1] - p->class_eoff[c]);
         }
         if (rc == ERI_OK && G > 1 && p->bits > 0) rc = upload(p, (void**)&p->d_stage, nullptr, (size_t)stage * sizeof(double));
+        // packed stream: words per quartet of each class
+        p->class_woff[0] = 0;
+        for (int c = 0; c < 256; ++c) {
+            const int64_t wpq = p->packed ? (ncart(c >> 6) * ncart((c >> 4) & 3) * ncart((c >> 2) & 3) * ncart(c & 3) +
+                                             512 / p->bits - 1) / (512 / p->bits) : 0;
+            p->class_woff[c + 1] = p->class_woff[c] + p->class_ring[c] * wpq;
+        }
     } catch (const std::bad_alloc&) {
         rc = ERI_ENOMEM;
     }
@@ -589,6 +599,7 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
         info->class_eri_off[c] = p->class_eoff[c];
         info->class_quartet_off[c] = p->class_qoff[c];
         info->class_scale_off[c] = p->class_soff[c];
+        info->class_word_off[c] = p->class_woff[c];
     }
     info->scale_block = p->scale_block;
     return ERI_OK;
@@ -640,6 +651,15 @@ static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, vo
     a.prims = p->d_prims;
     a.out_eri = out_eri ? out_eri + p->class_eoff[c] : nullptr;
     a.out_codes = out_codes ? (void*)((char*)out_codes + p->class_eoff[c] * p->code_bytes) : nullptr;
+    a.pack_bits = a.pack_per = 0;
+    a.pack_wpq = 0;
+    if (p->packed) {
+        a.out_codes = out_codes ? (void*)((char*)out_codes + p->class_woff[c] * 64) : nullptr;
+        a.pack_bits = p->bits;
+        a.pack_per = 512 / p->bits;
+        const int n = kernel_table(p->precision)[class_id5_of(c)].n_eriq;
+        a.pack_wpq = (n + a.pack_per - 1) / a.pack_per;
+    }
     a.out_scales = out_scales ? out_scales + p->class_soff[c] : nullptr;
     a.cn = p->cn;
     a.qmax = p->qmax;
@@ -649,13 +669,21 @@ static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, vo
     a.qbase = 0;
 }
 
+// Dynamic LDS of a launch: the packed stream stages every quartet's codes of
+// a workgroup (int16 for n <= 16, else int32).
+static size_t pack_lds(const eri_kernel_info& ki, const eri_class_args& a)
+{
+    if (!a.pack_bits || !a.out_codes) return 0;
+    return (size_t)ki.per_block * ki.n_eriq * (a.pack_bits > 16 ? 4 : 2);
+}
+
 static int launch_items(const eri_kernel_info& ki, eri_class_args& a, hipStream_t st)
 {
     const int64_t grid = (a.n_items + ki.per_block - 1) / ki.per_block;
     if (grid == 0) return ERI_OK;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     void* args[] = {&a};
-    ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, 0, st));
+    ERI_HIP_TRY(hipLaunchKernel(ki.fn, dim3((unsigned)grid), dim3(ki.block), args, pack_lds(ki, a), st));
     return ERI_OK;
 }
 
@@ -974,7 +1002,11 @@ static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, co
             rc = e == hipErrorOutOfMemory ? ERI_ENOMEM : ERI_EHIP;
         }
     };
-    if (p->code_bytes) {
+    if (p->packed) {
+        // at most 4 bytes per code plus one partial word per quartet
+        hip(hipMalloc(&o_codes, (size_t)max_vals * 4 + (size_t)max_q * 64));
+        hip(hipMalloc((void**)&o_scales, (size_t)max_q * sizeof(double)));
+    } else if (p->code_bytes) {
         hip(hipMalloc(&o_codes, (size_t)max_vals * p->code_bytes));
         hip(hipMalloc((void**)&o_scales, (size_t)max_q * sizeof(double)));
     } else {
@@ -1009,6 +1041,11 @@ static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, co
         a.ring = n;
         a.qbase = 0;
         a.n_items = n;
+        if (p->packed) {
+            a.pack_bits = p->bits;
+            a.pack_per = 512 / p->bits;
+            a.pack_wpq = (kernel_table(p->precision)[c5].n_eriq + a.pack_per - 1) / a.pack_per;
+        }
         double best = 0.0;
         int bestk = 0;
         for (int k = 0; k < ERI_MAXVAR && rc == ERI_OK; ++k) {

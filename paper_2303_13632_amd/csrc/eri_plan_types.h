@@ -48,4 +48,7 @@ struct eri_class_args {
     int32_t pad;
     int64_t ring;                   // output slots of the class: quartet q lands in slot q mod ring
     int64_t qbase;                  // class index of this launch's first quartet
+    int32_t pack_bits;              // > 0: out_codes is the packed stream of pack_bits-bit codes
+    int32_t pack_per;               // floor(512 / pack_bits) codes per 64-byte word
+    int64_t pack_wpq;               // words per quartet
 };

@@ -37,6 +37,7 @@ class EriError(RuntimeError):
 
 
 ERI_PLAN_ALL_QUARTETS = 1
+ERI_PLAN_PACKED = 2
 
 
 class PlanOpts(ctypes.Structure):
@@ -60,7 +61,8 @@ class PlanInfo(ctypes.Structure):
                 ("class_block", ctypes.c_int32 * 256), ("class_per_block", ctypes.c_int32 * 256),
                 ("class_n_variants", ctypes.c_int32 * 256), ("class_tag", ctypes.c_int32 * 256),
                 ("class_fp32", ctypes.c_int32 * 256), ("scale_block", ctypes.c_int32),
-                ("reserved2", ctypes.c_int32), ("class_scale_off", ctypes.c_int64 * 257)]
+                ("reserved2", ctypes.c_int32), ("class_scale_off", ctypes.c_int64 * 257),
+                ("class_word_off", ctypes.c_int64 * 257)]
 
 
 _vp = ctypes.c_void_p
@@ -141,7 +143,7 @@ class Plan:
     `schwarz`; its outputs form per-class rings bounded by `ring_bytes`."""
 
     def __init__(self, shells, quartets, precision="fp64", bits=16, device=0, schwarz=1e-10,
-                 ring_bytes=0, chunk_quartets=0, scale_block=1):
+                 ring_bytes=0, chunk_quartets=0, scale_block=1, packed=False):
         lib = load()
         self.shells = shells
         self.batched = quartets is None
@@ -151,8 +153,10 @@ class Plan:
         self.precision = precision
         self.bits = int(bits)
         self.device = int(device)
+        self.packed = bool(packed)
         opts = PlanOpts(PRECISIONS[precision], self.bits, self.device,
-                        ERI_PLAN_ALL_QUARTETS if self.batched else 0, float(schwarz),
+                        (ERI_PLAN_ALL_QUARTETS if self.batched else 0) | (ERI_PLAN_PACKED if packed else 0),
+                        float(schwarz),
                         int(ring_bytes), int(chunk_quartets), int(scale_block), 0)
         h = _vp()
         L = np.ascontiguousarray(shells["L"], dtype=np.int32)
@@ -187,6 +191,7 @@ class Plan:
         self.class_quartet_off = np.array(info.class_quartet_off[:], dtype=np.int64)
         self.class_scale_off = np.array(info.class_scale_off[:], dtype=np.int64)
         self.scale_block = int(info.scale_block)
+        self.class_word_off = np.array(info.class_word_off[:], dtype=np.int64)
         self.class_flops = np.array(info.class_flops[:], dtype=np.float64)
         self._read_variants(info)
         self._pos = None
@@ -250,7 +255,11 @@ class Plan:
         dev = torch.device("cuda", self.device)
         out_eri = torch.empty(max(self.out_values, 1), dtype=torch.float64, device=dev) if eri else None
         out_codes = out_scales = None
-        if codes and self.bits > 0:
+        if codes and self.bits > 0 and self.packed:
+            # the packed stream: 64-byte words, as int64 lanes
+            out_codes = torch.empty(max(8 * int(self.class_word_off[256]), 8), dtype=torch.int64, device=dev)
+            out_scales = torch.empty(max(self.out_blocks, 1), dtype=torch.float64, device=dev)
+        elif codes and self.bits > 0:
             out_codes = torch.empty(max(self.out_values, 1), dtype=code_dtype(self.bits), device=dev)
             out_scales = torch.empty(max(self.out_blocks, 1), dtype=torch.float64, device=dev)
         return out_eri, out_codes, out_scales
@@ -364,7 +373,7 @@ class Plan:
 
 
 # Name suffix of the generated kernel of each variant tag (eri_plan_info.class_tag)
-KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2", 6: "_w2x"}
+KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2", 6: "_w2xo2"}
 
 
 def _ncart(L):

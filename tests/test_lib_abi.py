@@ -125,10 +125,11 @@ def test_host_decompress_rejects_bad_arguments():
     assert lib.eri_plan_set_geometry(None, None, None) == eri.ERI_EINVAL
 
 
-def test_generator_refuses_unsafe_half_register_form():
+def test_generator_refuses_single_wave_two_subslot_form():
     """The generator raises (instead of silently skipping) for the kernel form
-    that returned wrong values on the GPU: two bra indices per lane at half
-    the registers with HRR staging in more chunks than the 32 KB form."""
+    that returned wrong values on the GPU in some runs: one wavefront holding
+    two bra indices per lane.  Classes with such a bra (an f-f or g-d pair)
+    get the two-wavefront kernels instead, as their default."""
     import importlib.util
     import os
     path = os.path.join(os.path.dirname(eri.__file__), "csrc", "codegen.py")
@@ -136,9 +137,10 @@ def test_generator_refuses_unsafe_half_register_form():
     G = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(G)
     ff = G.ClassPlan(3, 3, 3, 3)
-    assert G.unsafe_half_register(ff, 16384) and not G.occupancy_variant(ff)
-    with pytest.raises(ValueError):
-        G.emit_class(ff, "fp64", occupancy=2)
+    assert G.two_subslot(ff) and not G.occupancy_variant(ff)
+    for occ in (1, 2):
+        with pytest.raises(ValueError):
+            G.emit_class(ff, "fp64", occupancy=occ)
     # single-subslot classes keep their half-register forms, also with 3 chunks
     fdf = G.ClassPlan(3, 3, 2, 3)
     assert G.lds_chunks(fdf, 16384) == 3 and G.occupancy_variant(fdf)
