@@ -41,26 +41,57 @@ def build_workload(qpc, classes):
     return W.merge(parts)
 
 
-def cpu_baseline(classes, seconds):
-    """The oracle on a bounded sample of the same workload (first quartets of
-    every class), all host threads.  Returns a dict for the JSON line."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(classes, seconds, per_class_out=""):
+    """The oracle on a bounded sample of the same workload (n quartets of
+    every class from the same seeded generator), class by class on the host's
+    threads (at most 16), and a smaller sample of the same kind on one
+    thread.  Per-class oracle rates go to per_class_out (JSON) when given.
+    Returns a dict for the JSON line."""
     import oracle as O
     from paper_2303_13632_amd import workloads as W
-    threads = os.cpu_count() or 1
+    threads = min(16, os.cpu_count() or 1)
 
-    def run(n):
-        sh, q = W.merge([W.class_case(cid, n_quartets=n) for cid in classes])
-        t0 = time.perf_counter()
-        v, _, sizes = O.eri(sh, q, n_threads=threads)
-        return time.perf_counter() - t0, int(sizes.sum()), len(q)
+    def run(n, nthr, per=None):
+        tot_t, tot_e, tot_q = 0.0, 0, 0
+        for cid in classes:
+            sh, q = W.class_case(cid, n_quartets=n)
+            t0 = time.perf_counter()
+            _, _, sizes = O.eri(sh, q, n_threads=nthr)
+            dt = time.perf_counter() - t0
+            tot_t += dt
+            tot_e += int(sizes.sum())
+            tot_q += len(q)
+            if per is not None:
+                per[cid] = int(sizes.sum()) / dt / 1e9
+        return tot_t, tot_e, tot_q
 
-    t, neri, nq = run(1)
-    n = max(1, min(8192, int(seconds / max(t, 1e-3))))
-    if n > 1:
-        t, neri, nq = run(n)
+    t, neri, nq = run(1, threads)
+    n = max(4, min(8192, int(seconds / max(t, 1e-3))))
+    per = {}
+    t, neri, nq = run(n, threads, per)
+    n1 = max(1, n // (2 * threads))
+    t1, neri1, _ = run(n1, 1)
+    if per_class_out:
+        with open(per_class_out, "w") as f:
+            json.dump({"threads": threads, "quartets_per_class": n, "oracle_geris": per}, f, indent=1)
+    rates = sorted(per.values())
     return {"value": neri / t / 1e9, "unit": "GERIS", "cores": threads, "kind": "oracle",
-            "sample": "first %d quartets of each of the %d classes of the same workload (%d quartets, %d ERIs), "
-                      "%.1f s, FP64 uncompressed, Rys quadrature, OpenMP over quartets" % (n, len(classes), nq, neri, t)}
+            "cpu_model": cpu_model(),
+            "one_core_value": neri1 / t1 / 1e9,
+            "per_class_geris": {"min": rates[0], "median": rates[len(rates) // 2], "max": rates[-1]},
+            "sample": "%d quartets of each of the %d classes, same generator as the workload (%d quartets, %d ERIs), "
+                      "class by class, %.1f s, FP64 uncompressed, Rys quadrature, OpenMP over quartets; one "
+                      "thread: %d quartets per class, %.1f s" % (n, len(classes), nq, neri, t, n1, t1)}
 
 
 def main():
@@ -129,7 +160,8 @@ def main():
         "roofline": res["roofline"],
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(res["active"], args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(res["active"], args.cpu_seconds,
+                                           (args.per_class_out + ".oracle.json") if args.per_class_out else "")
     sec = [x for x in args.secondary.split(",") if x and x != "none"]
     if sec:
         out["secondary"] = {}

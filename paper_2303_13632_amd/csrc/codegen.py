@@ -35,6 +35,10 @@ import os
 
 REALS = {"fp64": "double", "mixed": "float"}
 
+# kernel name -> 1 if its packed-stream path stages codes in dynamic LDS (sized
+# at launch), 0 if in the kernel's own LDS once the HRR staging is consumed
+PACK_DYNAMIC_LDS = {}
+
 
 # ---------------------------------------------------------------------------
 # Cartesian bookkeeping
@@ -468,21 +472,144 @@ def emit_slot(em, idx):
     em("const int64_t oslot = gq < A.ring ? gq : gq % A.ring;")
 
 
-def emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, slow_expr, pack_tail):
+def emit_kx(em, cp):
+    """kx: the user-layout offset of ket index kcd (computed (ic, id) =
+    divmod(kcd, nd)); a ket pair of equal L stored swapped exchanges the
+    strides of its two shells."""
+    st = user_strides(cp)
+    nd = ncart(cp.d)
+    kn = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[2], nd, st[3])
+    if st[2] == nd * st[3] and st[3] == 1:
+        kn = "(int64_t)kcd"
+    if cp.c == cp.d and nd > 1:
+        ks = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[3], nd, st[2])
+        em("const int64_t kx = sk ? %s : %s;" % (ks, kn))
+    else:
+        em("const int64_t kx = %s;" % kn)
+
+
+def emit_pack_regs(em, cp, n, step, lane, guard, staged, ab_list, stage_base):
+    """Codes of a single-chunk slot kernel's packed path: the bra HRR of every
+    ket index this lane owns (j = lane, lane + step, ...) is quantised into
+    registers (fast multiply-by-reciprocal quantiser unless some 1/eps of the
+    workgroup overflows); after a barrier, when every lane has read the
+    ket-HRR staging, the codes go over that staging in user order."""
+    cb = comps(cp.b)
+    NIT = (n + step - 1) // step
+    em("int pkc[%d][%d];" % (NIT, len(ab_list)))
+    for fast in (True, False):
+        em.block("if (%s)" % ("!slow" if fast else "slow"))
+        em("#pragma unroll")
+        em.block("for (int it = 0; it < %d; ++it)" % NIT)
+        em("const int j = %s + it * %d;" % (lane, step))
+        em.block("if (%sj < %d)" % (guard, n))
+        for k, (ai, bi) in enumerate(ab_list):
+            expr = hrr_expr(bi, ai, staged, "ab")
+            q = ("eri_quantize_mul((double)(%s), inv, A.qmax)" if fast else
+                 "eri_quantize((double)(%s), eps, inv, A.qmax)") % expr
+            em("pkc[it][%d] = %s;" % (k, q))
+        em.end()
+        em.end()
+        em.end()
+    em("__syncthreads();   // every lane has read the ket-HRR staging")
+    em("#pragma unroll")
+    em.block("for (int it = 0; it < %d; ++it)" % NIT)
+    em("const int j = %s + it * %d;" % (lane, step))
+    em.block("if (%sj < %d)" % (guard, n))
+    em("const int kcd = j;")
+    emit_kx(em, cp)
+    emit_stage_codes(em, cp, len(ab_list), "s_u", stage_base, lambda k: "pkc[it][%d]" % k)
+    em.end()
+    em.end()
+
+
+def emit_stage_codes(em, cp, nab, stage, stage_base, code):
+    """Codes code(k) of bra index k at ket offset kx into the LDS staging
+    (int32 when the uniform flag wide is set, else int16), one branch for
+    all of them."""
+    cb = comps(cp.b)
+    for wide in (True, False):
+        em.block("if (wide)" if wide else "else")
+        t = "int32_t" if wide else "int16_t"
+        for k in range(nab):
+            ia_, ib_ = divmod(k, len(cb))
+            bra, _ = index_parts(cp, ia_, ib_, 0, 0)
+            em("reinterpret_cast<%s*>(%s)[%s(int)(%s + kx)] = (%s)%s;" % (t, stage, stage_base, bra, t, code(k)))
+        em.end()
+
+
+def narrow_chunking(NSU, nslot, NTE, NCD, n_eriq, NCH):
+    """Chunks of the packed codes pass that leave room in s_u (NSU doubles)
+    for the int16 codes of every slot: (chunk size, chunk count, byte
+    offset of the codes), or None when that takes more than one chunk
+    beyond twice the kernel's own."""
+    code_dbl = (nslot * n_eriq * 2 + 7) // 8
+    CHP = min(NCD, (NSU - code_dbl) // (nslot * NTE)) if NSU > code_dbl else 0
+    if NCH == 1 or CHP < 1:
+        return None
+    NCHP = (NCD + CHP - 1) // CHP
+    if NCHP > 2 * NCH + 1:
+        return None
+    return CHP, NCHP, nslot * NTE * CHP * 8
+
+
+def narrow_arg(G, nar, CH):
+    """emit_codes_pass's narrow argument for a kernel's chunk closures."""
+    if not nar:
+        return None
+    CHP, NCHP, off = nar
+
+    def enter():
+        G["CH"], G["t"] = CHP, "s_tp"
+
+    def leave():
+        G["CH"], G["t"] = CH, "s_t"
+    return NCHP, enter, leave, "(reinterpret_cast<unsigned char*>(s_u) + %d)" % off
+
+
+def emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, slow_expr, pack_tail, narrow=None):
     """Second pass of a slot kernel: quantise and store.  The container width
     and whether any reciprocal 1/eps of the workgroup overflows are uniform
     over the workgroup, so they are decided once: the common case stores
     through a typed pointer with the multiply-by-reciprocal quantiser; the
     general case (eps so small that 1/eps overflows: codes from x / eps) keeps
     the generic store.  For a packed stream (A.pack_bits > 0, uniform) the
-    codes are staged in LDS and pack_tail() writes the quartet's words."""
+    codes are staged in LDS and pack_tail() writes the quartet's words.
+    narrow = (chunk count, enter(), leave(), stage): with several chunks,
+    int16 codes go over the kernel's own LDS behind smaller chunks (enter()
+    and leave() switch the chunk closures), wider ones to dynamic LDS."""
     em.block("if (A.pack_bits)")
     em("const int wide = A.pack_bits > 16;")
-    for ch in range(NCH):
-        if NCH > 1:
-            ket_hrr_chunk(ch)
-        bra_hrr_chunk(ch, 3)
-    pack_tail()
+    if NCH == 1:
+        # single chunk: codes kept in registers (the accumulators are dead by
+        # now) while every lane reads the ket-HRR staging, then written over
+        # it and packed: no LDS beyond the kernel's own
+        em("const int slow = %s;" % slow_expr)
+        bra_hrr_chunk(0, 4)
+        pack_tail("s_u")
+    else:
+        em("const int slow = %s;" % slow_expr)
+
+        def staged(nch, stage):
+            for fast in (True, False):
+                em.block("if (!slow)" if fast else "else")
+                for ch in range(nch):
+                    ket_hrr_chunk(ch)
+                    bra_hrr_chunk(ch, 3, "fast" if fast else "slow", stage=stage)
+                em.end()
+            pack_tail(stage)
+        if narrow:
+            nchp, enter, leave, stage = narrow
+            em.block("if (!wide)")
+            enter()
+            staged(nchp, stage)
+            leave()
+            em.end()
+            em.block("else")
+            staged(NCH, "eri_pack_lds")
+            em.end()
+        else:
+            staged(NCH, "eri_pack_lds")
     em.end()
     em.block("else")
     em("const int slow = %s;" % slow_expr)
@@ -524,9 +651,10 @@ def emit_store_T(em, cp, outs):
     # packed stream: this lane's codes go to its LDS column, then it packs its quartet's words
     em("const int wide = A.pack_bits > 16;")
     for k, (nm, ix) in enumerate(outs):
-        em("eri_stage_code(i%d * (int)blockDim.x + (int)threadIdx.x, wide, eri_quantize(%s, eps, inv, A.qmax));" % (k, nm))
-    em("eri_pack_words(%d, (int)threadIdx.x, (int)blockDim.x, A.pack_bits, A.pack_per, A.pack_wpq, "
-       "reinterpret_cast<uint64_t*>(A.out_codes) + oslot * A.pack_wpq * 8, 0, 1);" % n)
+        em("eri_stage_code(eri_pack_lds, i%d * (int)blockDim.x + (int)threadIdx.x, wide, "
+           "eri_quantize(%s, eps, inv, A.qmax));" % (k, nm))
+    em("eri_pack_words(eri_pack_lds, %d, (int)threadIdx.x, (int)blockDim.x, A.pack_bits, A.pack_per, "
+       "(int)A.pack_wpq, reinterpret_cast<uint32_t*>(A.out_codes) + oslot * A.pack_wpq * 16);" % n)
     em.end()
     em.block("else")
     for k, (nm, ix) in enumerate(outs):
@@ -612,6 +740,11 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     # HRR staging s_t[slot][target e][cd chunk]
     em("__shared__ double s_u[%d];" % NSU)
     em("double (*s_t)[%d][%d] = reinterpret_cast<double (*)[%d][%d]>(s_u);" % (NTE, CH, NTE, CH))
+    G = {"CH": CH, "t": "s_t"}
+    nar = narrow_chunking(NSU, NSLOT, NTE, NCD, cp.n_eriq, NCH)
+    if nar:
+        em("double (*s_tp)[%d][%d] = reinterpret_cast<double (*)[%d][%d]>(s_u);   // packed codes pass"
+           % (NTE, nar[0], NTE, nar[0]))
     em("__shared__ double s_red[64];")
     em("const int lane = threadIdx.x;")
     em("const int slot = lane / %d;" % EP)
@@ -761,6 +894,7 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     ab_list = [(ai, bi) for ai in ca for bi in cb]
 
     def ket_hrr_chunk(ch):
+        CH, st = G["CH"], G["t"]
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         em("__syncthreads();")
         for s in range(S):
@@ -768,32 +902,37 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             for k in range(lo, hi):
                 ci, di = cd_list[k]
                 expr = hrr_expr(di, ci, lambda f, s=s: "(%s)%s" % (real, acc[(s, f)]), "cd")
-                em("s_t[slot][tg%d][%d] = (double)(%s);" % (s, k - lo, expr))
+                em("%s[slot][tg%d][%d] = (double)(%s);" % (st, s, k - lo, expr))
             em.end()
         em("__syncthreads();")
 
     stage_base = "slot * %d + " % cp.n_eriq
 
-    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True):
+    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True, stage="eri_pack_lds"):
+        CH, st = G["CH"], G["t"]
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
+        if pass_no == 4:
+            emit_pack_regs(em, cp, n, EP, "ls", "active && ",
+                           lambda e: "(%s)%s[slot][%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base)
+            return
         em.block("for (int j = ls; j < %d; j += %d)" % (n, EP))
         em.block("if (active)")
         em("const int kcd = %d + j;" % lo)
         for k, (ai, bi) in enumerate(ab_list):
-            expr = hrr_expr(bi, ai, lambda e: "(%s)s_t[slot][%d][j]" % (real, tgt_index[e]), "ab")
+            expr = hrr_expr(bi, ai, lambda e: "(%s)%s[slot][%d][j]" % (real, st, tgt_index[e]), "ab")
             em("const double x%d = (double)(%s);" % (k, expr))
-        # user-order index of (ab, kcd): computed (ic, id) = divmod(kcd, nd)
-        st = user_strides(cp)
-        nd = len(cd)
-        kn = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[2], nd, st[3])
-        if st[2] == nd * st[3] and st[3] == 1:
-            kn = "(int64_t)kcd"
-        if cp.c == cp.d and nd > 1:
-            ks = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[3], nd, st[2])
-            em("const int64_t kx = sk ? %s : %s;" % (ks, kn))
-        else:
-            em("const int64_t kx = %s;" % kn)
+        emit_kx(em, cp)
+        if pass_no == 3:
+            # codes into the LDS staging: multiply-by-reciprocal quantiser
+            # (ctype "fast") or the general one (1/eps overflows somewhere)
+            for k in range(len(ab_list)):
+                em("const int q%d = %s;" % (k, ("eri_quantize_mul(x%d, inv, A.qmax)" if ctype == "fast" else
+                                                "eri_quantize(x%d, eps, inv, A.qmax)") % k))
+            emit_stage_codes(em, cp, len(ab_list), stage, stage_base, lambda k: "q%d" % k)
+            em.end()
+            em.end()
+            return
         for k in range(len(ab_list)):
             ia_, ib_ = divmod(k, len(cb))
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
@@ -804,8 +943,6 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
                 elif store_values:
                     em("A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
-            elif pass_no == 3:
-                em("eri_stage_code(%s(int)(%s), wide, eri_quantize(x%d, eps, inv, A.qmax));" % (stage_base, ix, k))
             elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
             else:
@@ -840,12 +977,22 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     em("if (active && ls == 0 && A.out_scales) A.out_scales[oslot] = eps;")
     # with a single chunk its ket-HRR staging is still in LDS: only the bra
     # HRR is repeated (with several chunks, re-ordering them measured slower)
-    def pack_tail():
-        em("__syncthreads();")
-        em("if (active) eri_pack_words(%d, slot * %d, 1, A.pack_bits, A.pack_per, A.pack_wpq, "
-           "reinterpret_cast<uint64_t*>(A.out_codes) + oslot * A.pack_wpq * 8, ls, %d);" % (cp.n_eriq, cp.n_eriq, EP))
+    # 0: codes over the kernel's own LDS; 1: dynamic LDS; 2: dynamic LDS only
+    # for codes wider than 16 bits
+    PACK_DYNAMIC_LDS[name] = 0 if NCH == 1 else (2 if nar else 1)
+    # a single chunk stages the (int32 at most) codes of every slot over s_u
+    assert NCH > 1 or NSU * 8 >= NSLOT * cp.n_eriq * 4, name
 
-    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__syncthreads_or(__builtin_isinf(inv) ? 1 : 0)", pack_tail)
+    def pack_tail(stage):
+        # every lane of the workgroup packs the words of all its quartets
+        em("__syncthreads();")
+        em("eri_pack_group(%s, %d, (int)min((int64_t)%d, A.n_items - (int64_t)blockIdx.x * %d), A.pack_bits, "
+           "A.pack_per, (int)A.pack_wpq, reinterpret_cast<uint32_t*>(A.out_codes), "
+           "A.qbase + (int64_t)blockIdx.x * %d, A.ring, lane, 64);"
+           % (stage, cp.n_eriq, NSLOT, NSLOT, NSLOT))
+
+    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__syncthreads_or(__builtin_isinf(inv) ? 1 : 0)", pack_tail,
+                    narrow_arg(G, nar, CH))
     em.end()
     em.end()
     return name, em.text()
@@ -965,6 +1112,10 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
            % (NX, NX, NF * 64))
     em("__shared__ double s_red[128];")
     em("double (*s_t)[%d] = reinterpret_cast<double (*)[%d]>(s_u);" % (CH, CH))
+    G = {"CH": CH, "t": "s_t"}
+    nar = narrow_chunking(NSU, 1, NTE, NCD, cp.n_eriq, NCH)
+    if nar:
+        em("double (*s_tp)[%d] = reinterpret_cast<double (*)[%d]>(s_u);   // packed codes pass" % (nar[0], nar[0]))
     em("const int tid = threadIdx.x;")
     em("const int wv = tid >> 6;")
     em("const int ls = tid & 63;")
@@ -1099,37 +1250,44 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
     ab_list = [(ai, bi) for ai in ca for bi in cb]
 
     def ket_hrr_chunk(ch):
+        CH, st = G["CH"], G["t"]
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         em("__syncthreads();")
         em.block("if (active && tg0 >= 0)")
         for k in range(lo, hi):
             ci, di = cd_list[k]
             expr = hrr_expr(di, ci, lambda f: "(%s)%s" % (real, acc[f]), "cd")
-            em("s_t[tg0][%d] = (double)(%s);" % (k - lo, expr))
+            em("%s[tg0][%d] = (double)(%s);" % (st, k - lo, expr))
         em.end()
         em("__syncthreads();")
 
     stage_base = ""
 
-    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True):
+    def bra_hrr_chunk(ch, pass_no, ctype=None, store_values=True, stage="eri_pack_lds"):
+        CH, st = G["CH"], G["t"]
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         n = hi - lo
+        if pass_no == 4:
+            emit_pack_regs(em, cp, n, 128, "tid", "active && ",
+                           lambda e: "(%s)%s[%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base)
+            return
         em.block("for (int j = tid; j < %d; j += 128)" % n)
         em.block("if (active)")
         em("const int kcd = %d + j;" % lo)
         for k, (ai, bi) in enumerate(ab_list):
-            expr = hrr_expr(bi, ai, lambda e: "(%s)s_t[%d][j]" % (real, tgt_index[e]), "ab")
+            expr = hrr_expr(bi, ai, lambda e: "(%s)%s[%d][j]" % (real, st, tgt_index[e]), "ab")
             em("const double x%d = (double)(%s);" % (k, expr))
-        st = user_strides(cp)
-        nd = len(cd)
-        kn = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[2], nd, st[3])
-        if st[2] == nd * st[3] and st[3] == 1:
-            kn = "(int64_t)kcd"
-        if cp.c == cp.d and nd > 1:
-            ks = "(int64_t)(kcd / %d) * %d + (int64_t)(kcd %% %d) * %d" % (nd, st[3], nd, st[2])
-            em("const int64_t kx = sk ? %s : %s;" % (ks, kn))
-        else:
-            em("const int64_t kx = %s;" % kn)
+        emit_kx(em, cp)
+        if pass_no == 3:
+            # codes into the LDS staging: multiply-by-reciprocal quantiser
+            # (ctype "fast") or the general one (1/eps overflows somewhere)
+            for k in range(len(ab_list)):
+                em("const int q%d = %s;" % (k, ("eri_quantize_mul(x%d, inv, A.qmax)" if ctype == "fast" else
+                                                "eri_quantize(x%d, eps, inv, A.qmax)") % k))
+            emit_stage_codes(em, cp, len(ab_list), stage, stage_base, lambda k: "q%d" % k)
+            em.end()
+            em.end()
+            return
         for k in range(len(ab_list)):
             ia_, ib_ = divmod(k, len(cb))
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
@@ -1140,8 +1298,6 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
                 elif store_values:
                     em("A.out_eri[obase + %s] = x%d;" % (ix, k))
                 em("bmax = fmax(bmax, fabs(x%d));" % k)
-            elif pass_no == 3:
-                em("eri_stage_code(%s(int)(%s), wide, eri_quantize(x%d, eps, inv, A.qmax));" % (stage_base, ix, k))
             elif ctype is None:
                 em("eri_store_code(A.out_codes, obase + %s, A.code_bytes, eri_quantize(x%d, eps, inv, A.qmax));" % (ix, k))
             else:
@@ -1170,12 +1326,18 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
     em("if (active && tid == 0 && A.out_scales) A.out_scales[oslot] = eps;")
     # with a single chunk its ket-HRR staging is still in LDS: only the bra
     # HRR is repeated (with several chunks, re-ordering them measured slower)
-    def pack_tail():
-        em("__syncthreads();")
-        em("if (active) eri_pack_words(%d, 0, 1, A.pack_bits, A.pack_per, A.pack_wpq, "
-           "reinterpret_cast<uint64_t*>(A.out_codes) + oslot * A.pack_wpq * 8, tid, 128);" % cp.n_eriq)
+    PACK_DYNAMIC_LDS[name] = 0 if NCH == 1 else (2 if nar else 1)
+    # a single chunk stages the (int32 at most) codes over s_u
+    assert NCH > 1 or NSU * 8 >= cp.n_eriq * 4, name
 
-    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__builtin_isinf(inv) ? 1 : 0", pack_tail)
+    def pack_tail(stage):
+        em("__syncthreads();")
+        em("eri_pack_group(%s, %d, active ? 1 : 0, A.pack_bits, A.pack_per, (int)A.pack_wpq, "
+           "reinterpret_cast<uint32_t*>(A.out_codes), A.qbase + qi, A.ring, tid, 128);"
+           % (stage, cp.n_eriq))
+
+    emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, "__builtin_isinf(inv) ? 1 : 0", pack_tail,
+                    narrow_arg(G, nar, CH))
     em.end()
     em.end()
     return name, em.text()
@@ -1336,16 +1498,22 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
             c5 = class_id5(*user)
             lines_ = reg.setdefault(prec, [])
             fp32 = ", 1}" if prec == "mixed" else ", 0}"
+
+            def with_flags(info):
+                # fp32 flag, then whether the packed path stages in dynamic LDS
+                # (mode T kernels and multi-chunk slot kernels do)
+                name_ = info[len("{(const void*)"):].split(",")[0]
+                return info[:-1] + fp32[:-1] + ", %d}" % PACK_DYNAMIC_LDS.get(name_, 1)
             if two_subslot(cp):
                 # an 84-index bra: the default is the two-wavefront x-column kernel
                 name = kernel_name(prec, cp.user)
                 parts.append(emit_mode_W2(cp, prec, name, layout="xcol")[1])
-                lines_.append("    t[%d] = %s;" % (c5, w2_info(cp, name, TAG_DEFAULT)[:-1] + fp32))
+                lines_.append("    t[%d] = %s;" % (c5, with_flags(w2_info(cp, name, TAG_DEFAULT))))
                 infos = [w2_info(cp, name, TAG_DEFAULT)]
             else:
                 name, src = emit_class(cp, prec)
                 parts.append(src)
-                lines_.append("    t[%d] = %s;" % (c5, kernel_info_init(cp, name)[:-1] + fp32))
+                lines_.append("    t[%d] = %s;" % (c5, with_flags(kernel_info_init(cp, name))))
                 infos = variant_infos(cp, name)
             am = alternate_mode(cp) if max(user) <= 3 else None
             if am is not None:
@@ -1384,7 +1552,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                     infos.append(w2_info(cp, wname + "xo2", TAG_TWO_WAVES_XCOL_OCC2))
             assert len(infos) <= MAXVAR, (user, len(infos))
             for k, info in enumerate(infos):
-                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info[:-1] + fp32))
+                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, with_flags(info)))
         for prec, lines_ in reg.items():
             fname = "eri_register_%s_g%03d" % (prec, g // group)
             parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))

@@ -124,42 +124,187 @@ ERI_DEV int eri_quantize_mul(double x, double inv, double qmax)
 // Packed code stream written by the kernels themselves (Sec. III-B: 512-bit
 // output words of floor(512/n) n-bit codes, every quartet starting on a new
 // word).  A quartet's codes are first staged in LDS (int16 for n <= 16, else
-// int32; dynamic shared memory sized at launch), then packed: 64-bit lane q
-// of word w holds the n low bits of codes w*per + k whose bits overlap
-// [64 q, 64 q + 64), code k at bit k*n of the word.
+// int32; over the kernel's own HRR staging once every lane has read it, or in
+// dynamic shared memory sized at launch), then packed by the functions
+// below.
 // ---------------------------------------------------------------------------
 extern __shared__ __align__(16) unsigned char eri_pack_lds[];
 
-ERI_DEV void eri_stage_code(int idx, int wide, int q)
+ERI_DEV void eri_stage_code(void* stage, int idx, int wide, int q)
 {
     if (wide)
-        reinterpret_cast<int32_t*>(eri_pack_lds)[idx] = q;
+        reinterpret_cast<int32_t*>(stage)[idx] = q;
     else
-        reinterpret_cast<int16_t*>(eri_pack_lds)[idx] = (int16_t)q;
+        reinterpret_cast<int16_t*>(stage)[idx] = (int16_t)q;
 }
 
-// Packs the n codes staged at eri_pack_lds[(first code) off, stride] into
-// 8 * wpq 64-bit lanes of `out`, lanes lane, lane + nlanes, ...
-ERI_DEV void eri_pack_words(int n, int off, int stride, int bits, int per, int64_t wpq, uint64_t* __restrict__ out,
-                            int lane, int nlanes)
+ERI_DEV int eri_staged_code(const void* stage, int idx, int wide)
+{
+    return wide ? reinterpret_cast<const int32_t*>(stage)[idx] : (int)reinterpret_cast<const int16_t*>(stage)[idx];
+}
+
+// 32-bit dword q4 (0..15) of one 512-bit word whose first code is staged at
+// stage[base] (its k-th code at base + k * stride; navail codes present):
+// the n low bits of every code k whose bits overlap [32 q4, 32 q4 + 32),
+// code k at bit k * n of the word.  n = 8, 16 and 32 take aligned fast paths.
+// Otherwise floor(x / n) for x < 512 is taken as (x * ceil(2^16 / n)) >> 16,
+// exact there for 2 <= n <= 32, and a code starting at bit p of the dword
+// (-n < p < 32) lands as the high half of the 64-bit code << (p + 32).
+ERI_DEV uint32_t eri_pack_dword(const void* stage, int base, int stride, int navail, int q4, int bits, int per,
+                                int wide)
+{
+    // reads are clamped to the last code present (navail >= 1), so they
+    // issue unconditionally; absent codes count as 0
+    const int last = navail - 1;
+    if (bits == 16) {
+        const int k = 2 * q4;
+        const uint32_t c0 = (uint16_t)eri_staged_code(stage, base + min(k, last) * stride, 0);
+        const uint32_t c1 = (uint16_t)eri_staged_code(stage, base + min(k + 1, last) * stride, 0);
+        return (k < navail ? c0 : 0u) | ((k + 1 < navail ? c1 : 0u) << 16);
+    }
+    if (bits == 32) {
+        const uint32_t c = (uint32_t)eri_staged_code(stage, base + min(q4, last) * stride, 1);
+        return q4 < navail ? c : 0u;
+    }
+    if (bits == 8) {
+        uint32_t c[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            c[t] = (uint8_t)eri_staged_code(stage, base + min(4 * q4 + t, last) * stride, 0);
+        uint32_t v = 0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            v |= (4 * q4 + t < navail ? c[t] : 0u) << (8 * t);
+        return v;
+    }
+    const uint32_t mask = (1u << bits) - 1u;   // 2 <= bits < 32 here
+    const unsigned magic = (65535u + (unsigned)bits) / (unsigned)bits;
+    const int lo = 32 * q4;
+    const int k0 = (int)(((unsigned)lo * magic) >> 16);
+    const int k1 = min(min(per - 1, (int)(((unsigned)(lo + 31) * magic) >> 16)), navail - 1);
+    uint32_t v = 0;
+    if (bits > 8) {
+        int c[5];   // at most 5 codes of n > 8 bits overlap a dword
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+            c[t] = eri_staged_code(stage, base + min(k0 + t, last) * stride, wide);
+#pragma unroll
+        for (int t = 0; t < 5; ++t)
+            c[t] = k0 + t > k1 ? 0 : c[t];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+            const int sh = (k0 + t) * bits - lo + 32;   // in (32 - n, 64)
+            v |= (uint32_t)(((uint64_t)((uint32_t)c[t] & mask) << (sh & 63)) >> 32);
+        }
+    } else {
+        for (int k = k0; k <= k1; ++k) {
+            const int sh = k * bits - lo + 32;
+            v |= (uint32_t)(((uint64_t)((uint32_t)eri_staged_code(stage, base + k * stride, wide) & mask) << sh) >> 32);
+        }
+    }
+    return v;
+}
+
+// One thread packs the n codes of its own quartet, staged at
+// stage[off + k * stride], into the 16 * wpq dwords at out.
+ERI_DEV void eri_pack_words(const void* stage, int n, int off, int stride, int bits, int per, int wpq,
+                            uint32_t* __restrict__ out)
 {
     const int wide = bits > 16;
-    const uint64_t mask = (1ull << bits) - 1ull;   // bits <= 32
-    for (int64_t u = lane; u < 8 * wpq; u += nlanes) {
-        const int w = (int)(u >> 3), q8 = (int)(u & 7);
-        const int first = w * per;
-        const int k0 = (64 * q8) / bits;
-        const int k1 = min(per - 1, (64 * q8 + 63) / bits);
-        uint64_t v = 0;
-        for (int k = k0; k <= k1 && first + k < n; ++k) {
-            const int idx = (first + k) * stride + off;
-            const int c = wide ? reinterpret_cast<const int32_t*>(eri_pack_lds)[idx]
-                               : (int)reinterpret_cast<const int16_t*>(eri_pack_lds)[idx];
-            const uint64_t f = (uint64_t)(int64_t)c & mask;
-            const int sh = k * bits - 64 * q8;   // in (-bits, 64)
-            v |= sh >= 0 ? (f << sh) : (f >> -sh);
+    for (int d = 0; d < 16 * wpq; ++d) {
+        const int w = d >> 4;
+        out[d] = eri_pack_dword(stage, off + w * per * stride, stride, n - w * per, d & 15, bits, per, wide);
+    }
+}
+
+// Quartet s of a workgroup's nq and the remainder r of f = s * m + r, the
+// quotient taken in float and corrected by one step (exact for f < 2^24).
+ERI_DEV void eri_split_index(int f, int m, float rm, int& s, int& r)
+{
+    s = (int)((float)f * rm);
+    r = f - s * m;
+    if (r < 0) {
+        --s;
+        r += m;
+    } else if (r >= m) {
+        ++s;
+        r -= m;
+    }
+}
+
+ERI_DEV int64_t eri_ring_slot(int64_t g, int64_t ring) { return g < ring ? g : g % ring; }
+
+// n = BITS with a fixed unit of U consecutive codes (U * BITS a multiple of
+// 32): one thread reads a unit's codes and writes its dwords with constant
+// shifts; a word holds ceil(per / U) units, the last one cut at dword 16.
+template <int BITS, int U>
+ERI_DEV void eri_pack_group_fixed(const void* stage, int n, int nq, int wpq, uint32_t* __restrict__ out,
+                                  int64_t gq0, int64_t ring, int lane, int nlanes)
+{
+    constexpr int PER = 512 / BITS;
+    constexpr int UPW = (PER + U - 1) / U;
+    constexpr int D = U * BITS / 32;
+    constexpr uint32_t MASK = BITS == 32 ? 0xffffffffu : (1u << (BITS & 31)) - 1u;
+    static_assert(U * BITS % 32 == 0, "a unit ends on a dword");
+    const int uq = UPW * wpq;
+    const float rl = 1.0f / (float)uq;
+    for (int f = lane; f < nq * uq; f += nlanes) {
+        int s, r;
+        eri_split_index(f, uq, rl, s, r);
+        const int w = r / UPW;
+        const int g = r - w * UPW;
+        const int k0 = w * PER + g * U;
+        const int navail = min(PER - g * U, n - k0);
+        // every read stays inside the quartet's codes (index clamped to its
+        // last one), so the reads issue together; absent codes count as 0
+        uint32_t c[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t)
+            c[t] = (uint32_t)eri_staged_code(stage, s * n + min(k0 + t, n - 1), BITS > 16) & MASK;
+#pragma unroll
+        for (int t = 0; t < U; ++t)
+            c[t] = t < navail ? c[t] : 0u;
+        uint32_t d[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) d[i] = 0u;
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int b = t * BITS;
+            d[b / 32] |= c[t] << (b % 32);
+            if (b % 32 + BITS > 32) d[b / 32 + 1] |= c[t] >> (32 - b % 32);
         }
-        out[u] = v;
+        uint32_t* o = out + eri_ring_slot(gq0 + s, ring) * (16 * wpq) + 16 * w + g * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+            if (g * D + i < 16) o[i] = d[i];
+    }
+}
+
+// The threads lane, lane + nlanes, ... of a workgroup pack the codes of its
+// nq consecutive quartets (quartet s staged at stage[s * n + k], k < n) into
+// the words of their output slots (class quartet gq0 + s, wrapped into the
+// ring): 16 * wpq dwords per quartet, consecutive threads on consecutive
+// units.  n = 8, 12, 16, 32 take fixed units; other widths one dword per
+// thread.
+ERI_DEV void eri_pack_group(const void* stage, int n, int nq, int bits, int per, int wpq,
+                            uint32_t* __restrict__ out, int64_t gq0, int64_t ring, int lane, int nlanes)
+{
+    switch (bits) {
+    case 12: eri_pack_group_fixed<12, 8>(stage, n, nq, wpq, out, gq0, ring, lane, nlanes); return;
+    case 16: eri_pack_group_fixed<16, 8>(stage, n, nq, wpq, out, gq0, ring, lane, nlanes); return;
+    case 8: eri_pack_group_fixed<8, 16>(stage, n, nq, wpq, out, gq0, ring, lane, nlanes); return;
+    case 32: eri_pack_group_fixed<32, 4>(stage, n, nq, wpq, out, gq0, ring, lane, nlanes); return;
+    default: break;
+    }
+    const int wide = bits > 16;
+    const int lq = 16 * wpq;
+    const float rl = 1.0f / (float)lq;
+    for (int f = lane; f < nq * lq; f += nlanes) {
+        int s, d;
+        eri_split_index(f, lq, rl, s, d);
+        const int w = d >> 4;
+        out[eri_ring_slot(gq0 + s, ring) * lq + d] =
+            eri_pack_dword(stage, s * n + w * per, 1, n - w * per, d & 15, bits, per, wide);
     }
 }
 

@@ -16,6 +16,7 @@ struct eri_kernel_info {
                          // at half the registers, 6 two wavefronts split by x-columns at half the
                          // registers (the default of an f-f bra is the two-wavefront x-column form)
     int32_t fp32;        // 1: VRR/HRR in FP32 (FP32-mixed kernel); 0: FP64
+    int32_t pack_dyn;    // packed stream stages codes in dynamic LDS: 0 never, 1 always, 2 for n > 16
 };
 
 // Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by

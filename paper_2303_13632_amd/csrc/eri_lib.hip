@@ -669,11 +669,13 @@ static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, vo
     a.qbase = 0;
 }
 
-// Dynamic LDS of a launch: the packed stream stages every quartet's codes of
-// a workgroup (int16 for n <= 16, else int32).
+// Dynamic LDS of a launch: where the kernel stages the packed stream's codes
+// there (pack_dyn 1 always, 2 for codes wider than 16 bits), every quartet's
+// codes of a workgroup (int16 for n <= 16, else int32).
 static size_t pack_lds(const eri_kernel_info& ki, const eri_class_args& a)
 {
-    if (!a.pack_bits || !a.out_codes) return 0;
+    if (!a.pack_bits || !a.out_codes || !ki.pack_dyn) return 0;
+    if (ki.pack_dyn == 2 && a.pack_bits <= 16) return 0;
     return (size_t)ki.per_block * ki.n_eriq * (a.pack_bits > 16 ? 4 : 2);
 }
 

@@ -57,7 +57,7 @@ def _quartet_offsets(plan):
     return np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
 
 
-FUSED_CLASSES = (0, 5, 21, 85, 106, 170, 187, 231, 238, 246, 250, 255)
+FUSED_CLASSES = (0, 5, 21, 85, 95, 106, 170, 187, 231, 238, 245, 246, 250, 255)
 
 
 @pytest.mark.parametrize("bits", [3, 7, 12, 16, 20, 32])
@@ -65,15 +65,16 @@ def test_fused_packed_stream(bits):
     """Plans with ERI_PLAN_PACKED write the packed stream from the ERI kernels
     (codes staged in LDS, no container array): its bytes equal the oracle's
     packing of the oracle's compression of the same doubles, every launch
-    variant of every class (lane-per-quartet, slot and two-wavefront kernels,
-    ragged workgroups)."""
+    variant of every class at 12 and 20 bits (lane-per-quartet, slot and
+    two-wavefront kernels, ragged workgroups; codes of several-chunk kernels
+    over their own LDS at 12 bits, in dynamic LDS at 20)."""
     from paper_2303_13632_amd import eri
     parts = [W.class_case(cid, n_quartets=67, seed=W.SEED_BASE + 82) for cid in FUSED_CLASSES]
     sh, q = W.merge(parts)
     plan = eri.Plan(sh, q, bits=bits, packed=True)
     nv = plan.class_n_variants
     off = _quartet_offsets(plan)
-    for k in range(int(nv.max()) if bits == 12 else 1):
+    for k in range(int(nv.max()) if bits in (12, 20) else 1):
         print("bits %d variant pass %d" % (bits, k), flush=True)
         plan.set_variants(np.where(nv > k, k, 0).astype(np.int32))
         e, c, s = plan.alloc(eri=True, codes=True)

@@ -261,3 +261,73 @@ def test_scale_block(case, G):
     assert np.all(np.abs(codes * step - ref_plan) <= step / 2 + 4 * np.spacing(bmax) + 1e-12)
     if G == 64 and case == "ss_k3":
         assert len(np.unique(np.abs(codes))) > 100     # a block resolves the values within it
+
+
+def _tiny_scale_case():
+    """Lane-per-quartet, slot and two-wavefront classes whose quartets cycle
+    through three magnitudes: normal; the a shell's coefficients times 1e-306
+    (b_max around 1e-310, so 1/eps overflows at every width); times 1e-300
+    (eps normal or subnormal depending on n).  Normal and tiny quartets share
+    workgroups, so the fused kernels' divide path (eps subnormal) runs beside
+    the multiply path."""
+    parts = [W.class_case(cid, n_quartets=45, seed=W.SEED_BASE + 91)
+             for cid in (W.class_id(1, 0, 1, 0), W.class_id(3, 2, 3, 2), W.class_id(3, 3, 3, 2), 255)]
+    shells, quartets = W.merge(parts)
+    coefs = shells["coefs"].copy()
+    for t, (a, _, _, _) in enumerate(quartets):
+        f = (1.0, 1e-306, 1e-300)[t % 3]
+        coefs[shells["off"][a]:shells["off"][a + 1]] *= f
+    shells["coefs"] = coefs
+    return shells, quartets
+
+
+@pytest.mark.parametrize("bits", [8, 16, 32])
+def test_subnormal_scales(bits):
+    """Fused codes and scales bit-identical to the oracle's compressor of the
+    GPU doubles when some eps are subnormal (codes from x / eps), every launch
+    variant at 16 bits; FP64 values within 1e-12 of the oracle."""
+    from paper_2303_13632_amd import eri
+    shells, quartets = _tiny_scale_case()
+    plan = eri.Plan(shells, quartets, bits=bits)
+    nv = plan.class_n_variants
+    sizes = np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets)
+    blk = _blocks(sizes)
+    ref, ref_off, rsizes = O.eri(shells, quartets, n_threads=THREADS)
+    for k in range(int(nv.max()) if bits == 16 else 1):
+        print("bits %d variant pass %d" % (bits, k), flush=True)
+        plan.set_variants(np.where(nv > k, k, 0).astype(np.int32))
+        e, c, s = plan.alloc(eri=True, codes=True)
+        plan.compute(e, c, s)
+        torch.cuda.synchronize()
+        vals = e.cpu().numpy()[: plan.n_eri]
+        codes = c.cpu().numpy()[: plan.n_eri].astype(np.int32)
+        scales = s.cpu().numpy()[: plan.n_quartets]
+        oc, oe = O.compress(bits, vals, blk)
+        assert np.array_equal(oe, scales), (bits, k)
+        assert np.array_equal(oc, codes), (bits, k)
+        got = plan.to_user(vals)
+        assert float(np.abs(got - ref).max()) <= 1e-12
+    with np.errstate(divide="ignore", over="ignore"):
+        inv = 1.0 / scales
+    n_div = int(np.sum((scales > 0) & np.isinf(inv)))
+    n_mul = int(np.sum(np.isfinite(inv) & (scales > 0)))
+    print("bits %d: %d quartets through x/eps, %d through x*(1/eps)" % (bits, n_div, n_mul))
+    assert n_div >= 40 and n_mul >= 40
+
+
+def test_subnormal_scales_packed():
+    """The packed stream (12-bit) of the same case: bytes equal to the
+    oracle's packing of the oracle's compression of the GPU doubles."""
+    from paper_2303_13632_amd import eri
+    shells, quartets = _tiny_scale_case()
+    plan = eri.Plan(shells, quartets, bits=12, packed=True)
+    sizes = np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets)
+    blk = _blocks(sizes)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    vals = e.cpu().numpy()[: plan.n_eri]
+    oc, oe = O.compress(12, vals, blk)
+    ref, _ = O.pack(12, oc, blk)
+    assert np.array_equal(c.cpu().numpy().view(np.uint8)[: len(ref)], ref)
+    assert np.array_equal(s.cpu().numpy()[: plan.n_quartets], oe)
