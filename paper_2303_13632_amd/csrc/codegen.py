@@ -436,7 +436,7 @@ def emit_mode_T(cp, prec, name):
                     expr = hrr_expr(bi, ai, lambda e, ci=ci, di=di: y[(e, ci, di)], "ab")
                     em("const double %s = (double)(%s);" % (nm, expr))
                     outs.append((nm, (ia, ib_, ic, id_)))
-    emit_store_T(em, cp, outs)
+    emit_store_T(em, cp, outs, prec)
     em.end()
     return name, em.text()
 
@@ -629,13 +629,72 @@ def emit_codes_pass(em, NCH, ket_hrr_chunk, bra_hrr_chunk, slow_expr, pack_tail,
     em.end()
 
 
-def emit_store_T(em, cp, outs):
+def adjoint_form(cp, prec):
+    """Kernels that the adjoint launches: FP64 classes reached from user
+    shells up to d by one derivative shift (L+1, L-1 or L+2 on one centre),
+    so at most one shell above d."""
+    return prec == "fp64" and sum(1 for l in cp.user if l > 2) <= 1
+
+
+def emit_adj_T(em, outs):
+    """Adjoint launch of a lane-per-quartet kernel: the lane's ERIs go into
+    its quartet's gradient sums instead of the outputs."""
+    em.block("if (A.adj.map)")
+    em("eri_adj_quartet aq;")
+    em("eri_adj_begin(A.adj, t, aq);")
+    em("double g0 = 0.0, g1 = 0.0, g2 = 0.0;")
+    for k, (nm, _) in enumerate(outs):
+        em("eri_adj_add(A.adj, aq, i%d, %s, g0, g1, g2);" % (k, nm))
+    em("eri_adj_finish(A.adj, t, aq, g0, g1, g2);")
+    em("return;")
+    em.end()
+
+
+def emit_adj_slot(em, ket_hrr_chunk, bra_hrr_chunk, NCH, lane, ls, base, n, active, slot, nslot, off, room):
+    """Adjoint launch of a slot or two-wavefront kernel (every thread of the
+    workgroup takes it, so its barriers are uniform): the HRR outputs go into
+    per-thread gradient sums, which the quartet's n threads add up through
+    s_red; thread 0 of the quartet hands them to the gradients.  Each
+    quartet's Gbar row is first copied into the free part of s_u (doubles
+    off .. off + room, behind the HRR staging) when the workgroup's rows fit,
+    so that the HRR outputs gather it from LDS."""
+    em.block("if (A.adj.map)")
+    em("eri_adj_quartet aq;")
+    em("if (%s) eri_adj_begin(A.adj, qi, aq);" % active)
+    em("double g0 = 0.0, g1 = 0.0, g2 = 0.0;")
+    if room > 0:
+        em("__syncthreads();   // the primitive staging in s_u is free")
+        em.block("if (%d * A.adj.n_eriq <= %d)" % (nslot, room))
+        em("double* s_g = s_u + %d + %s * A.adj.n_eriq;" % (off, slot))
+        em("if (%s) for (int t = %s; t < A.adj.n_eriq; t += %d) s_g[t] = aq.g[t];" % (active, ls, n))
+        em("if (%s) aq.g = s_g;" % active)
+        em.end()
+    for ch in range(NCH):
+        ket_hrr_chunk(ch)
+        bra_hrr_chunk(ch, 5)
+    for v in ("g0", "g1", "g2"):
+        em("__syncthreads();")
+        em("s_red[%s] = %s;" % (lane, v))
+        em("__syncthreads();")
+        em.block("if (%s && %s == 0)" % (active, ls))
+        em("double sum = 0.0;")
+        em("for (int k = 0; k < %d; ++k) sum += s_red[%s + k];" % (n, base))
+        em("%s = sum;" % v)
+        em.end()
+    em("if (%s && %s == 0) eri_adj_finish(A.adj, qi, aq, g0, g1, g2);" % (active, ls))
+    em("return;")
+    em.end()
+
+
+def emit_store_T(em, cp, outs, prec):
     n = cp.n_eriq
     emit_slot(em, "t")
     em("const int64_t obase = oslot * %d;" % n)
     for k, (nm, ix) in enumerate(outs):
         bra, ket = index_parts(cp, *ix)
         em("const int i%d = %s + %s;" % (k, bra, ket))
+    if adjoint_form(cp, prec):
+        emit_adj_T(em, outs)
     em.block("if (A.out_eri)")
     for k, (nm, ix) in enumerate(outs):
         em("A.out_eri[obase + i%d] = %s;" % (k, nm))
@@ -937,7 +996,9 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
             ia_, ib_ = divmod(k, len(cb))
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
             ix = "%s + kx" % bra
-            if pass_no == 1:
+            if pass_no == 5:
+                em("eri_adj_add(A.adj, aq, (int)(%s), x%d, g0, g1, g2);" % (ix, k))
+            elif pass_no == 1:
                 if store_values is None:
                     em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 elif store_values:
@@ -951,6 +1012,9 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
         em.end()
         em.end()
 
+    if adjoint_form(cp, prec):
+        emit_adj_slot(em, ket_hrr_chunk, bra_hrr_chunk, NCH, "lane", "ls", "sbase", EP, "active", "slot", NSLOT,
+                      NSLOT * NTE * CH, NSU - NSLOT * NTE * CH)
     em("double bmax = 0.0;")
     # first pass: b_max, and the FP64 values when requested, decided once (the
     # output pointer is uniform) except in the half-register kernels, where
@@ -1292,7 +1356,9 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
             ia_, ib_ = divmod(k, len(cb))
             bra, _ = index_parts(cp, ia_, ib_, 0, 0)
             ix = "%s + kx" % bra
-            if pass_no == 1:
+            if pass_no == 5:
+                em("eri_adj_add(A.adj, aq, (int)(%s), x%d, g0, g1, g2);" % (ix, k))
+            elif pass_no == 1:
                 if store_values is None:
                     em("if (A.out_eri) A.out_eri[obase + %s] = x%d;" % (ix, k))
                 elif store_values:
@@ -1306,6 +1372,9 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
         em.end()
         em.end()
 
+    if adjoint_form(cp, prec):
+        emit_adj_slot(em, ket_hrr_chunk, bra_hrr_chunk, NCH, "tid", "tid", "0", 128, "active", "0", 1,
+                      NTE * CH, NSU - NTE * CH)
     em("double bmax = 0.0;")
     # first pass: b_max, and the FP64 values when requested (decided once:
     # the output pointer is uniform)

@@ -20,13 +20,15 @@
 // Pipeline per class and chunk of quartets: user items (P1, P2) -> for each
 // derivative kind a derived item list (derive kernel; for the exponent kinds
 // one item per primitive of the differentiated shell, compacted by a scan) ->
-// the forward kernel of the derived class writes FP64 blocks into scratch ->
-// the contraction kernel maps each derived block onto Gbar.  Contraction
-// blocks sum into an LDS copy of the gradient, which each block adds into its
-// own slice of a partial-sum buffer (no atomics on global memory); one final
-// kernel adds the slices into the caller's arrays.  Gradients too large for
-// LDS fall back to global FP64 atomics.  Either way the order of the atomic
-// additions, and so the last bits of the gradient sums, may vary between
+// the class kernel of the derived class, launched in its adjoint form: every
+// derived ERI is multiplied into Gbar of the user ERI it derives from as it
+// leaves the HRR (a per-kind map gives the user ERI, axis and factor), the
+// quartet's three sums are added up over its threads, and one FP64 atomic
+// per axis adds them into a slice of the gradient.  No derived integral is
+// stored.  The atomics go to one of up to 1024 slices of the gradient
+// (workgroup index modulo the slice count), which one final kernel adds into
+// the caller's arrays in slice order; the order of the atomic additions
+// within a slice, and so the last bits of the gradient sums, may vary between
 // calls.  The scalar L itself is summed in a fixed order: every quartet's
 // contribution is written to a buffer and one workgroup adds a pass's buffer
 // with compensated (two-sum) arithmetic into a double-double running total,
@@ -51,10 +53,10 @@ namespace {
 enum { DK_BASE = -1, DK_PLUS = 0, DK_MINUS = 1, DK_E0 = 2, DK_E2 = 3 };
 
 constexpr int BWD_MAXL = 2;                       // shells of the differentiated basis
-constexpr int64_t BWD_SCRATCH_MAX = (int64_t)1 << 28;   // doubles (2 GiB)
 constexpr int64_t BWD_CHUNK_MAX = (int64_t)1 << 22;     // quartets per pass
-constexpr int BWD_SLICES = 1024;                  // contraction blocks (partial-sum slices)
-constexpr int BWD_LDS_MAX = 4096;                 // gradient entries kept in LDS (32 KB)
+constexpr int64_t BWD_GBAR_MAX = (int64_t)1 << 27;      // doubles of a pass's D_ab D_cd rows (1 GiB)
+constexpr int64_t BWD_SLICE_DOUBLES = (int64_t)1 << 24; // gradient slices in all (128 MB)
+constexpr int BWD_SLICES_MAX = 1024;
 
 __host__ __device__ inline int kind_shift(int kind) { return kind == DK_PLUS ? 1 : kind == DK_MINUS ? -1 : kind == DK_E2 ? 2 : 0; }
 
@@ -69,12 +71,10 @@ struct eri_bwd_state {
     eri_item* d_uall = nullptr;  // explicit plans: user items in plan order
     eri_item* d_uitems = nullptr;
     eri_item* d_ditems = nullptr;
-    double* d_scratch = nullptr;
     int64_t* d_bf = nullptr;     // first basis function of each shell
     int64_t* d_poff = nullptr;   // first primitive of each shell (the caller's layout)
     int64_t nbf = 0;
     int64_t chunk_cap = 0;
-    int64_t scratch_elems = 0;
     int kmax[BWD_MAXL + 1] = {};  // largest K among shells of each L
     int kmax_all = 1;
     bool full = false;            // derived records built (else energy only)
@@ -84,7 +84,13 @@ struct eri_bwd_state {
     void* d_scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
     int64_t n_grad = 0;           // 3 n_shells + n_prims
-    double* d_part = nullptr;     // BWD_SLICES partial gradients (LDS mode)
+    int32_t* d_maps = nullptr;    // contraction maps of the derived launches
+    double* d_gbar = nullptr;     // density form: D_ab D_cd rows of a pass's user quartets
+    double* d_part = nullptr;     // n_slices gradient slices of n_grad entries
+    double* d_spare = nullptr;    // one slice for the timing launches of the variant choice
+    int n_slices = 1;
+    int64_t gbar_elems = 0;
+    std::vector<int64_t> map_off = std::vector<int64_t>(256 * 20, -1);   // [class][kind + 1][position]
     double* d_eitem = nullptr;    // per quartet of a pass: its contribution to L
     double* d_eacc = nullptr;     // running total of L: (high, low) double-double
     int32_t* h_pin = nullptr;     // pinned host word for scan totals
@@ -98,10 +104,9 @@ struct eri_bwd_state {
 void eri_bwd_free(eri_bwd_state* b)
 {
     if (!b) return;
-    void* ptrs[] = {b->d_pairs,  b->d_prims, b->d_dmap,   b->d_uall,     b->d_uitems,   b->d_ditems,
-                    b->d_scratch, b->d_bf,    b->d_poff,   b->d_cnt,      b->d_off,      b->d_origin,
-                    b->d_scan_tmp, b->d_part, b->d_usorted, b->d_key,     b->d_sort_tmp, b->d_eitem,
-                    b->d_eacc};
+    void* ptrs[] = {b->d_pairs,    b->d_prims, b->d_dmap,    b->d_uall, b->d_uitems,   b->d_ditems,
+                    b->d_maps,     b->d_gbar,  b->d_part, b->d_spare, b->d_bf,    b->d_poff,    b->d_cnt,  b->d_off,      b->d_origin,
+                    b->d_scan_tmp, b->d_usorted, b->d_key,   b->d_sort_tmp, b->d_eitem, b->d_eacc};
     for (void* x : ptrs)
         if (x) (void)hipFree(x);
     if (b->h_pin) (void)hipHostFree(b->h_pin);
@@ -113,22 +118,6 @@ namespace {
 // ---------------------------------------------------------------------------
 // Device kernels
 // ---------------------------------------------------------------------------
-// Components (lx, ly, lz) of L = 0..4 in shell order (x^L first).
-__constant__ signed char c_comp[5][15][3] = {
-    {{0, 0, 0}},
-    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
-    {{2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2}},
-    {{3, 0, 0}, {2, 1, 0}, {2, 0, 1}, {1, 2, 0}, {1, 1, 1}, {1, 0, 2}, {0, 3, 0}, {0, 2, 1}, {0, 1, 2}, {0, 0, 3}},
-    {{4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0}, {1, 2, 1}, {1, 1, 2}, {1, 0, 3},
-     {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3}, {0, 0, 4}},
-};
-
-__device__ __forceinline__ int comp_index(int lx, int ly, int lz)
-{
-    const int m = ly + lz;   // L - lx
-    return m * (m + 1) / 2 + lz;
-}
-
 // Derived items of one kind: the user item (P1, P2) with the pair `pair`
 // replaced by its derived record for user position `pos` of that pair, put in
 // the orientation of the derived class kernel (kswap: its bra is pair 2;
@@ -217,25 +206,48 @@ __global__ __launch_bounds__(256) void eri_bwd_origin_kernel(const int32_t* __re
     for (int k = 0; k < cnt[i]; ++k) origin[off[i] + k] = (int32_t)i | (k << 24);
 }
 
-__global__ __launch_bounds__(256) void eri_bwd_zero_kernel(double* __restrict__ x, int64_t n)
+// Density form: row i of the pass holds Gbar = D_ab D_cd over the ERIs of
+// user item i (user layout, components in shell order).
+__global__ __launch_bounds__(256) void eri_bwd_gbar_kernel(const eri_item* __restrict__ uitems, int64_t m,
+                                                           const eri_shell_pair* __restrict__ pairs,
+                                                           const int64_t* __restrict__ bf,
+                                                           const double* __restrict__ dens, int64_t nbf, int nc0,
+                                                           int nc1, int nc2, int nc3, double* __restrict__ out)
 {
-    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) x[t] = 0.0;
+    const int n_eriq = nc0 * nc1 * nc2 * nc3;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < m * n_eriq; t += (int64_t)gridDim.x * 256) {
+        const int64_t i = t / n_eriq;
+        int rem = (int)(t - i * n_eriq);
+        const int c3 = rem % nc3; rem /= nc3;
+        const int c2 = rem % nc2; rem /= nc2;
+        const int c1 = rem % nc1;
+        const int c0 = rem / nc1;
+        const eri_item u = uitems[i];
+        const eri_shell_pair P1 = pairs[u.bra & 0x7fffffff], P2 = pairs[u.ket & 0x7fffffff];
+        const int64_t f0 = bf[u.bra < 0 ? P1.sb : P1.sa], f1 = bf[u.bra < 0 ? P1.sa : P1.sb];
+        const int64_t f2 = bf[u.ket < 0 ? P2.sb : P2.sa], f3 = bf[u.ket < 0 ? P2.sa : P2.sb];
+        out[t] = dens[(f0 + c0) * nbf + f1 + c1] * dens[(f2 + c2) * nbf + f3 + c3];
+    }
 }
 
-// grad_c / grad_e += sum over slices, in slice order.
-__global__ __launch_bounds__(256) void eri_bwd_reduce_kernel(const double* __restrict__ part, int64_t n_grad,
-                                                             int64_t ns3, double* __restrict__ grad_c,
+// grad_c / grad_e += the sum of the slices, in slice order.
+__global__ __launch_bounds__(256) void eri_bwd_reduce_kernel(const double* __restrict__ part, int n_slices,
+                                                             int64_t n_grad, int64_t ns3, double* __restrict__ grad_c,
                                                              double* __restrict__ grad_e)
 {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= n_grad) return;
     double v = 0.0;
-    for (int b = 0; b < BWD_SLICES; ++b) v += part[(int64_t)b * n_grad + t];
-    if (t < ns3) {
-        if (grad_c) grad_c[t] += v;
-    } else if (grad_e) {
+    for (int b = 0; b < n_slices; ++b) v += part[(int64_t)b * n_grad + t];
+    if (t < ns3)
+        grad_c[t] += v;
+    else
         grad_e[t - ns3] += v;
-    }
+}
+
+__global__ __launch_bounds__(256) void eri_bwd_zero_kernel(double* __restrict__ x, int64_t n)
+{
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) x[t] = 0.0;
 }
 
 // Error-free sum of two doubles (Knuth's two-sum): s + e == a + b exactly.
@@ -289,145 +301,6 @@ __global__ void eri_bwd_energy_out_kernel(double* __restrict__ acc, double* __re
     }
 }
 
-struct bwd_contract_args {
-    const eri_item* uitems;
-    int64_t n;                  // items (derived blocks)
-    const int32_t* origin;      // exponent kinds: item -> quartet | (primitive << 24); else null
-    const int32_t* orig;        // quartet -> its index in the pass (plan order), for dl
-    const eri_shell_pair* pairs;
-    const double* blk;          // derived blocks, one per item
-    const double* dl;           // dL/dERI in plan layout, or null
-    int64_t dl_base;            // index in dl of the first ERI of the pass's first quartet
-    const double* dens;         // density (nbf x nbf), or null
-    int64_t nbf;
-    const int64_t* bf;
-    const int64_t* poff;
-    double* grad_c;             // global atomics mode
-    double* grad_e;
-    double* eitem;              // base kind: per-item contributions to L
-    double* part;               // LDS mode: slices of n_grad partial sums, or null
-    int64_t n_grad;
-    int64_t ns3;                // 3 n_shells
-    int32_t L[4];               // user angular momenta of the class
-    int32_t pos;                // differentiated user position (kinds other than base)
-    int32_t kind;
-    int32_t group;              // lanes per item: 1, 2, ..., 64
-    int32_t degen;              // weight quartets by their degeneracy in the full sum
-};
-
-// Groups of `group` lanes per item: sum over the quartet's ERIs of Gbar times
-// the mapped derived ERIs, reduced across the group.
-__global__ __launch_bounds__(256) void eri_bwd_contract_kernel(bwd_contract_args A)
-{
-    extern __shared__ double s_g[];
-    const bool lds = A.part != nullptr;
-    if (lds) {
-        for (int64_t t = threadIdx.x; t < A.n_grad; t += 256) s_g[t] = 0.0;
-        __syncthreads();
-    }
-    const int G = A.group;
-    const int gl = threadIdx.x & (G - 1);
-    const int64_t per_block = 256 / G;
-    int nc[4], nd[4];
-    for (int x = 0; x < 4; ++x) {
-        nc[x] = (A.L[x] + 1) * (A.L[x] + 2) / 2;
-        nd[x] = nc[x];
-    }
-    const int dpos = A.kind == DK_BASE ? 0 : A.pos;
-    const int Ld = A.L[dpos] + kind_shift(A.kind);
-    nd[dpos] = (Ld + 1) * (Ld + 2) / 2;
-    const int n_eriq = nc[0] * nc[1] * nc[2] * nc[3];
-    const int st[4] = {nd[1] * nd[2] * nd[3], nd[2] * nd[3], nd[3], 1};
-    const int64_t nblk = (int64_t)nd[0] * st[0];
-    for (int64_t j = (int64_t)blockIdx.x * per_block + threadIdx.x / G; j < A.n; j += (int64_t)gridDim.x * per_block) {
-        const int64_t i = A.origin ? (int64_t)(A.origin[j] & 0xffffff) : j;
-        const int k = A.origin ? (A.origin[j] >> 24) : 0;
-        const eri_item u = A.uitems[i];
-        const int32_t p1 = u.bra & 0x7fffffff, p2 = u.ket & 0x7fffffff;
-        const eri_shell_pair P1 = A.pairs[p1], P2 = A.pairs[p2];
-        int32_t sh[4];
-        sh[0] = u.bra < 0 ? P1.sb : P1.sa;
-        sh[1] = u.bra < 0 ? P1.sa : P1.sb;
-        sh[2] = u.ket < 0 ? P2.sb : P2.sa;
-        sh[3] = u.ket < 0 ? P2.sa : P2.sb;
-        const double* b = A.blk + j * nblk;
-        double w = 1.0;
-        if (A.degen) {
-            if (sh[0] != sh[1]) w *= 2.0;
-            if (sh[2] != sh[3]) w *= 2.0;
-            if (p1 != p2) w *= 2.0;
-        }
-        int64_t f0 = 0, f1 = 0, f2 = 0, f3 = 0;
-        if (!A.dl) {
-            f0 = A.bf[sh[0]]; f1 = A.bf[sh[1]]; f2 = A.bf[sh[2]]; f3 = A.bf[sh[3]];
-        }
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-        for (int o = gl; o < n_eriq; o += G) {
-            int ci[4];
-            int rem = o;
-            ci[3] = rem % nc[3]; rem /= nc[3];
-            ci[2] = rem % nc[2]; rem /= nc[2];
-            ci[1] = rem % nc[1]; rem /= nc[1];
-            ci[0] = rem;
-            double g;
-            if (A.dl) {
-                g = A.dl[A.dl_base + (int64_t)A.orig[i] * n_eriq + o];
-            } else {
-                g = A.dens[(f0 + ci[0]) * A.nbf + f1 + ci[1]] * A.dens[(f2 + ci[2]) * A.nbf + f3 + ci[3]];
-            }
-            if (g == 0.0) continue;
-            if (A.kind == DK_BASE || A.kind == DK_E0) {
-                acc0 += g * b[o];
-                continue;
-            }
-            int base = 0;
-            for (int x = 0; x < 4; ++x)
-                if (x != dpos) base += ci[x] * st[x];
-            const int sd = st[dpos];
-            const int La = A.L[dpos];
-            const int lx = c_comp[La][ci[dpos]][0], ly = c_comp[La][ci[dpos]][1], lz = c_comp[La][ci[dpos]][2];
-            if (A.kind == DK_PLUS) {
-                acc0 += g * b[base + comp_index(lx + 1, ly, lz) * sd];
-                acc1 += g * b[base + comp_index(lx, ly + 1, lz) * sd];
-                acc2 += g * b[base + comp_index(lx, ly, lz + 1) * sd];
-            } else if (A.kind == DK_MINUS) {
-                if (lx) acc0 -= g * lx * b[base + comp_index(lx - 1, ly, lz) * sd];
-                if (ly) acc1 -= g * ly * b[base + comp_index(lx, ly - 1, lz) * sd];
-                if (lz) acc2 -= g * lz * b[base + comp_index(lx, ly, lz - 1) * sd];
-            } else {
-                acc0 += g * (b[base + comp_index(lx + 2, ly, lz) * sd] + b[base + comp_index(lx, ly + 2, lz) * sd] +
-                             b[base + comp_index(lx, ly, lz + 2) * sd]);
-            }
-        }
-        for (int s = G >> 1; s > 0; s >>= 1) {
-            acc0 += __shfl_xor(acc0, s);
-            acc1 += __shfl_xor(acc1, s);
-            acc2 += __shfl_xor(acc2, s);
-        }
-        if (gl != 0) continue;
-        acc0 *= w; acc1 *= w; acc2 *= w;
-        double* gc = lds ? s_g : A.grad_c;
-        double* ge = lds ? s_g + A.ns3 : A.grad_e;
-        if (A.kind == DK_BASE) {
-            A.eitem[j] = acc0;
-        } else if (A.kind == DK_PLUS || A.kind == DK_MINUS) {
-            const double v[3] = {acc0, acc1, acc2};
-            for (int x = 0; x < 3; ++x) {
-                atomicAdd(gc + 3 * (int64_t)sh[dpos] + x, v[x]);
-                atomicAdd(gc + 3 * (int64_t)sh[3] + x, -v[x]);
-            }
-        } else {
-            atomicAdd(ge + A.poff[sh[dpos]] + k, acc0);
-        }
-    }
-    if (lds) {
-        __syncthreads();
-        double* mine = A.part + (int64_t)blockIdx.x * A.n_grad;
-        for (int64_t t = threadIdx.x; t < A.n_grad; t += 256)
-            if (s_g[t] != 0.0) mine[t] += s_g[t];
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host: derived shells, derived pair records and the per-record map
 // ---------------------------------------------------------------------------
@@ -459,6 +332,88 @@ bool stored_reversed(const shell_set& s, int32_t x, int32_t y, bool by_score)
 {
     if (s.L[x] != s.L[y]) return s.L[x] < s.L[y];
     return by_score && x != y && vrr_score(s, y, x) < vrr_score(s, x, y);
+}
+
+// Derived class of a kind and its n_ERIQ.
+static void derived_ls(const int L[4], int pos, int kind, int Lp[4])
+{
+    for (int x = 0; x < 4; ++x) Lp[x] = L[x];
+    if (kind != DK_BASE) Lp[pos] += kind_shift(kind);
+}
+
+// Components of a Cartesian shell of angular momentum L, in shell order
+// (x^L first): index m (m + 1) / 2 + lz with m = L - lx.
+static int comp_index_h(int lx, int ly, int lz)
+{
+    const int m = ly + lz;
+    return m * (m + 1) / 2 + lz;
+}
+
+static void comp_of(int L, int idx, int& lx, int& ly, int& lz)
+{
+    int m = 0;
+    while ((m + 1) * (m + 2) / 2 <= idx) ++m;
+    lz = idx - m * (m + 1) / 2;
+    ly = m - lz;
+    lx = L - m;
+}
+
+// Contraction map of the derived launch of (user class L, kind, position):
+// for every ERI of the derived class (user layout of that class) four slots,
+// up to three of them used (user ERI o, axis, factor; -1 unused), appended
+// to `out`.  PLUS: (a+1_x) <- o = a, axis x, +1; MINUS: (a-1_x) <- a, axis
+// x, -a_x; E0 and the base kind: the same ERI; E2: (a+2_x) <- a, axis 0.
+static void adj_map(const int L[4], int kind, int pos, std::vector<int32_t>& out)
+{
+    int Lp[4];
+    derived_ls(L, pos, kind, Lp);
+    int nc[4], nd[4];
+    for (int x = 0; x < 4; ++x) {
+        nc[x] = ncart(L[x]);
+        nd[x] = ncart(Lp[x]);
+    }
+    const int64_t st[4] = {(int64_t)nd[1] * nd[2] * nd[3], (int64_t)nd[2] * nd[3], nd[3], 1};
+    const int64_t base0 = (int64_t)out.size();
+    out.resize(base0 + 4 * nd[0] * st[0], -1);
+    auto put = [&](int64_t o2, int32_t v) {
+        for (int e = 0; e < 3; ++e)
+            if (out[base0 + 4 * o2 + e] < 0) {
+                out[base0 + 4 * o2 + e] = v;
+                return;
+            }
+    };
+    const int n_eriq = nc[0] * nc[1] * nc[2] * nc[3];
+    for (int o = 0; o < n_eriq; ++o) {
+        int ci[4], rem = o;
+        ci[3] = rem % nc[3]; rem /= nc[3];
+        ci[2] = rem % nc[2]; rem /= nc[2];
+        ci[1] = rem % nc[1]; rem /= nc[1];
+        ci[0] = rem;
+        const int32_t enc = o;
+        if (kind == DK_BASE || kind == DK_E0) {
+            put(o, enc);
+            continue;
+        }
+        int64_t base = 0;
+        for (int x = 0; x < 4; ++x)
+            if (x != pos) base += ci[x] * st[x];
+        int l[3];
+        comp_of(L[pos], ci[pos], l[0], l[1], l[2]);
+        for (int ax = 0; ax < 3; ++ax) {
+            int m[3] = {l[0], l[1], l[2]};
+            if (kind == DK_PLUS) {
+                m[ax] += 1;
+                put(base + comp_index_h(m[0], m[1], m[2]) * st[pos], enc | ax << 23);
+            } else if (kind == DK_MINUS) {
+                if (l[ax] == 0) continue;
+                m[ax] -= 1;
+                put(base + comp_index_h(m[0], m[1], m[2]) * st[pos], enc | ax << 23 | l[ax] << 25);
+            } else {
+                m[ax] += 2;
+                put(base + comp_index_h(m[0], m[1], m[2]) * st[pos], enc);
+            }
+        }
+    }
 }
 
 // full = false builds only the base records (energy-only calls).
@@ -588,23 +543,34 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
     for (int64_t s = 0; s < ns; ++s) bf[s + 1] = bf[s] + ncart(orig.L[s]);
     st->nbf = bf[ns];
     // ---- pass sizes ------------------------------------------------------------
-    int64_t maxcount = 0, maxnd = 1;
+    int64_t maxcount = 0;
+    for (int c = 0; c < 256; ++c) maxcount = std::max(maxcount, p->class_count[c]);
+    for (int l = 0; l <= BWD_MAXL; ++l) st->kmax_all = std::max(st->kmax_all, st->kmax[l]);
+    // passes take up to BWD_CHUNK_MAX quartets (nothing per derived ERI is stored)
+    st->chunk_cap = std::max<int64_t>(1, std::min(maxcount, BWD_CHUNK_MAX));
+    if (p->pass_cap > 0) st->chunk_cap = std::min(st->chunk_cap, p->pass_cap);
+    // density form: a pass of class c holds at most BWD_GBAR_MAX / n_eriq(c)
+    // quartets (its D_ab D_cd rows)
+    for (int c = 0; c < 256; ++c) {
+        if (!p->class_count[c]) continue;
+        const int64_t ne = (int64_t)ncart(c >> 6) * ncart((c >> 4) & 3) * ncart((c >> 2) & 3) * ncart(c & 3);
+        const int64_t q = std::min({p->class_count[c], st->chunk_cap, std::max<int64_t>(1, BWD_GBAR_MAX / ne)});
+        st->gbar_elems = std::max(st->gbar_elems, q * ne);
+    }
+    // ---- contraction maps ----------------------------------------------------
+    std::vector<int32_t> maps;
     for (int c = 0; c < 256; ++c) {
         if (!p->class_count[c]) continue;
         const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
-        int64_t base = 1;
-        for (int x = 0; x < 4; ++x) base *= ncart(L[x]);
-        int64_t nd = base;
-        for (int x = 0; x < 4; ++x) nd = std::max<int64_t>(nd, base / ncart(L[x]) * ncart(L[x] + 2));
-        maxcount = std::max(maxcount, p->class_count[c]);
-        maxnd = std::max(maxnd, nd);
+        for (int kind = DK_BASE; kind <= DK_E2; ++kind)
+            for (int pos = 0; pos < 4; ++pos) {
+                if (kind == DK_BASE ? pos != 0 : !full) continue;
+                if ((kind == DK_PLUS || kind == DK_MINUS) && pos == 3) continue;
+                if (kind == DK_MINUS && L[pos] == 0) continue;
+                st->map_off[(c * 5 + kind + 1) * 4 + pos] = (int64_t)maps.size();
+                adj_map(L, kind, pos, maps);
+            }
     }
-    for (int l = 0; l <= BWD_MAXL; ++l) st->kmax_all = std::max(st->kmax_all, st->kmax[l]);
-    // passes of small classes take up to BWD_CHUNK_MAX quartets; larger derived
-    // blocks shorten the pass so that one kind's blocks fit the scratch
-    st->chunk_cap = std::max<int64_t>(1, std::min(maxcount, BWD_CHUNK_MAX));
-    if (p->pass_cap > 0) st->chunk_cap = std::min(st->chunk_cap, p->pass_cap);
-    st->scratch_elems = std::min(BWD_SCRATCH_MAX, st->chunk_cap * maxnd * st->kmax_all);
     int64_t nprim_all = 0;
     for (int64_t s = 0; s < ns; ++s) nprim_all = std::max<int64_t>(nprim_all, orig.off[s] + orig.K[s]);
     st->n_grad = 3 * ns + nprim_all;
@@ -642,7 +608,13 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
         }
     }
     up((void**)&st->d_sort_tmp, nullptr, std::max<size_t>(st->sort_tmp_bytes, 64));
-    if (st->n_grad <= BWD_LDS_MAX) up((void**)&st->d_part, nullptr, (size_t)BWD_SLICES * st->n_grad * sizeof(double));
+    up((void**)&st->d_maps, maps.data(), maps.size() * sizeof(int32_t));
+    up((void**)&st->d_gbar, nullptr, (size_t)std::max<int64_t>(st->gbar_elems, 1) * sizeof(double));
+    if (full) {
+        st->n_slices = (int)std::max<int64_t>(1, std::min<int64_t>(BWD_SLICES_MAX, BWD_SLICE_DOUBLES / st->n_grad));
+        up((void**)&st->d_part, nullptr, (size_t)st->n_slices * st->n_grad * sizeof(double));
+        up((void**)&st->d_spare, nullptr, (size_t)st->n_grad * sizeof(double));
+    }
     up((void**)&st->d_eitem, nullptr, (size_t)st->chunk_cap * sizeof(double));
     up((void**)&st->d_eacc, nullptr, 2 * sizeof(double));
     if (rc == ERI_OK) {
@@ -652,7 +624,6 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
             rc = ERI_ENOMEM;
         }
     }
-    up((void**)&st->d_scratch, nullptr, (size_t)st->scratch_elems * sizeof(double));
     up((void**)&st->d_bf, bf.data(), bf.size() * sizeof(int64_t));
     up((void**)&st->d_poff, p->sh_off.empty() ? nullptr : p->sh_off.data(), p->sh_off.size() * sizeof(int64_t));
     if (rc != ERI_OK) {
@@ -663,20 +634,12 @@ int build_state(eri_plan* p, eri_bwd_state*& out, bool full)
     return ERI_OK;
 }
 
-// Derived class of a kind and its n_ERIQ.
-static void derived_ls(const int L[4], int pos, int kind, int Lp[4])
-{
-    for (int x = 0; x < 4; ++x) Lp[x] = L[x];
-    if (kind != DK_BASE) Lp[pos] += kind_shift(kind);
-}
-
 struct bwd_call {
     const double* dl;
     const double* dens;
     double* grad_c;
     double* grad_e;
     double* energy;
-    bool lds;
 };
 
 // Derived items of one kind in the bra/ket order of kernel `ki`.
@@ -748,8 +711,8 @@ static int pick_variant(eri_bwd_state* st, int c5, const eri_class_args& full, h
     return ERI_OK;
 }
 
-// One derived kind over `m` items: derive, forward kernel of the derived
-// class into scratch, contraction.
+// One derived kind over `m` items: derive, then the derived class's kernel in
+// its adjoint form (contraction with Gbar into the gradients or L's buffer).
 static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const eri_item* uitems, int64_t m,
                     const int32_t* origin, const int32_t* orig, int pos, int kind, int64_t q0, const bwd_call& call)
 {
@@ -758,56 +721,56 @@ static int run_kind(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, con
     int Lp[4];
     derived_ls(L, pos, kind, Lp);
     const eri_kernel_info& ki = kernel_table(ERI_FP64)[class_id5(Lp[0], Lp[1], Lp[2], Lp[3])];
-    if (!ki.fn) return ERI_EUNSUPPORTED;
+    const int64_t moff = st->map_off[(c * 5 + kind + 1) * 4 + pos];
+    // the kernels have the adjoint form for classes with at most one shell
+    // above d (every derived class of user shells up to d)
+    const int above_d = (Lp[0] > 2) + (Lp[1] > 2) + (Lp[2] > 2) + (Lp[3] > 2);
+    if (!ki.fn || moff < 0 || above_d > 1) return ERI_EUNSUPPORTED;
     eri_class_args a;
     std::memset(&a, 0, sizeof(a));
     a.items = st->d_ditems;
     a.n_items = m;
     a.pairs = st->d_pairs;
     a.prims = st->d_prims;
-    a.out_eri = st->d_scratch;
     a.ring = m;
     a.qbase = 0;
+    eri_adj_ctx& C = a.adj;
+    C.map = st->d_maps + moff;
+    C.uitems = uitems;
+    C.origin = origin;
+    C.orig = orig;
+    C.pairs = st->d_pairs;
+    const int n_eriq = ncart(L[0]) * ncart(L[1]) * ncart(L[2]) * ncart(L[3]);
+    if (call.dl) {
+        C.gbar = call.dl;
+        C.g_base = p->class_eoff[c] + q0 * (int64_t)n_eriq;
+    } else {
+        C.gbar = st->d_gbar;   // rows in the pass's (sorted) order
+        C.g_base = 0;
+        C.orig = nullptr;
+    }
+    C.poff = st->d_poff;
+    C.grad = st->d_part;
+    C.slice_stride = st->n_grad;
+    C.ns3 = 3 * (int64_t)p->sh_L.size();
+    C.n_slices = st->n_slices;
+    C.eitem = st->d_eitem;
+    C.n_eriq = n_eriq;
+    C.kind = kind;
+    C.pos = pos;
+    C.degen = p->batched ? 1 : 0;
+    // variants are timed in the adjoint form, their gradient sums going to a
+    // spare slice (and L's buffer, which the real launch then rewrites)
     const eri_kernel_info* kv = &ki;
-    ERI_TRY(pick_variant(st, class_id5(Lp[0], Lp[1], Lp[2], Lp[3]), a, strm, uitems, origin, pos, kind, Lp, kv));
+    eri_class_args t = a;
+    t.adj.grad = st->d_spare;
+    t.adj.n_slices = 1;
+    ERI_TRY(pick_variant(st, class_id5(Lp[0], Lp[1], Lp[2], Lp[3]), t, strm, uitems, origin, pos, kind, Lp, kv));
     ERI_TRY(derive_items(st, strm, uitems, m, origin, pos, kind, Lp, *kv));
     const int64_t grid = (m + kv->per_block - 1) / kv->per_block;
     if (grid > INT32_MAX) return ERI_EUNSUPPORTED;
     void* args[] = {&a};
     ERI_HIP_TRY(hipLaunchKernel(kv->fn, dim3((unsigned)grid), dim3(kv->block), args, 0, strm));
-    bwd_contract_args ca;
-    std::memset(&ca, 0, sizeof(ca));
-    ca.uitems = uitems;
-    ca.n = m;
-    ca.origin = origin;
-    ca.orig = orig;
-    ca.pairs = st->d_pairs;
-    ca.blk = st->d_scratch;
-    ca.dl = call.dl;
-    const int n_eriq = ncart(L[0]) * ncart(L[1]) * ncart(L[2]) * ncart(L[3]);
-    ca.dl_base = p->class_eoff[c] + q0 * (int64_t)n_eriq;
-    ca.dens = call.dens;
-    ca.nbf = st->nbf;
-    ca.bf = st->d_bf;
-    ca.poff = st->d_poff;
-    ca.grad_c = call.grad_c;
-    ca.grad_e = call.grad_e;
-    ca.eitem = st->d_eitem;
-    ca.part = call.lds && kind != DK_BASE ? st->d_part : nullptr;
-    ca.n_grad = st->n_grad;
-    ca.ns3 = 3 * (int64_t)p->sh_L.size();
-    for (int x = 0; x < 4; ++x) ca.L[x] = L[x];
-    ca.pos = pos;
-    ca.kind = kind;
-    int G = 1;
-    while (G < 64 && G < n_eriq) G <<= 1;
-    ca.group = G;
-    ca.degen = p->batched ? 1 : 0;
-    const int64_t per_block = 256 / G;
-    const int64_t blocks = std::min<int64_t>(BWD_SLICES, (m + per_block - 1) / per_block);
-    const size_t lds = ca.part ? (size_t)st->n_grad * sizeof(double) : 0;
-    hipLaunchKernelGGL(eri_bwd_contract_kernel, dim3((unsigned)blocks), dim3(256), lds, strm, ca);
-    ERI_HIP_TRY(hipGetLastError());
     if (kind == DK_BASE) {
         hipLaunchKernelGGL(eri_bwd_energy_sum_kernel, dim3(1), dim3(256), 0, strm, st->d_eitem, m, st->d_eacc);
         ERI_HIP_TRY(hipGetLastError());
@@ -819,14 +782,10 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd
 {
     const int64_t n = p->class_count[c];
     const int L[4] = {c >> 6, (c >> 4) & 3, (c >> 2) & 3, c & 3};
-    // largest derived block of the class, and quartets per pass
-    int64_t maxnd = 1;
-    for (int x = 0; x < 4; ++x) {
-        int64_t nd = 1;
-        for (int y = 0; y < 4; ++y) nd *= ncart(L[y] + (y == x ? 2 : 0));
-        maxnd = std::max(maxnd, nd);
-    }
-    const int64_t chunk = std::max<int64_t>(1, std::min(st->chunk_cap, st->scratch_elems / (maxnd * st->kmax_all)));
+    const int nc[4] = {ncart(L[0]), ncart(L[1]), ncart(L[2]), ncart(L[3])};
+    const int64_t n_eriq = (int64_t)nc[0] * nc[1] * nc[2] * nc[3];
+    const int64_t chunk = call.dens ? std::max<int64_t>(1, std::min(st->chunk_cap, st->gbar_elems / n_eriq))
+                                    : st->chunk_cap;
     // passes: explicit plans walk the class's plan positions; batched plans
     // walk each entry of the class (quartet index within the class = qoff + j)
     struct pass_src {
@@ -874,6 +833,13 @@ int run_class(eri_plan* p, eri_bwd_state* st, int c, hipStream_t strm, const bwd
         hipLaunchKernelGGL(eri_bwd_gather_kernel, dim3(gm), dim3(256), 0, strm, uitems, m, orig, st->d_usorted);
         ERI_HIP_TRY(hipGetLastError());
         uitems = st->d_usorted;
+        if (call.dens) {
+            const int64_t tot = m * n_eriq;
+            const unsigned gg = (unsigned)std::min<int64_t>((tot + 255) / 256, 65536);
+            hipLaunchKernelGGL(eri_bwd_gbar_kernel, dim3(gg), dim3(256), 0, strm, uitems, m, st->d_pairs, st->d_bf,
+                               call.dens, st->nbf, nc[0], nc[1], nc[2], nc[3], st->d_gbar);
+            ERI_HIP_TRY(hipGetLastError());
+        }
         if (call.energy) ERI_TRY(run_kind(p, st, c, strm, uitems, m, nullptr, orig, 0, DK_BASE, q0, call));
         if (!call.grad_c) continue;
         for (int x = 0; x < 3; ++x) {
@@ -935,10 +901,10 @@ extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, co
     if (rc == ERI_OK && density && nbf != p->bwd->nbf) rc = ERI_EINVAL;
     eri_bwd_state* st = p->bwd;
     hipStream_t strm = (hipStream_t)stream;
-    const bwd_call call{dl_deri, density, grad_centers, grad_exps, energy, st && st->d_part != nullptr};
-    if (rc == ERI_OK && call.lds) {
+    const bwd_call call{dl_deri, density, grad_centers, grad_exps, energy};
+    if (rc == ERI_OK && grad_centers) {
         hipLaunchKernelGGL(eri_bwd_zero_kernel, dim3(1024), dim3(256), 0, strm, st->d_part,
-                           (int64_t)BWD_SLICES * st->n_grad);
+                           (int64_t)st->n_slices * st->n_grad);
         if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
     }
     if (rc == ERI_OK && energy) {
@@ -947,9 +913,10 @@ extern "C" int eri_backward(eri_plan* p, void* stream, const double* dl_deri, co
     }
     for (int c = 0; c < 256 && rc == ERI_OK; ++c)
         if (p->class_count[c]) rc = run_class(p, st, c, strm, call);
-    if (rc == ERI_OK && call.lds) {
+    if (rc == ERI_OK && grad_centers) {
         hipLaunchKernelGGL(eri_bwd_reduce_kernel, dim3((unsigned)((st->n_grad + 255) / 256)), dim3(256), 0, strm,
-                           st->d_part, st->n_grad, 3 * (int64_t)p->sh_L.size(), grad_centers, grad_exps);
+                           st->d_part, st->n_slices, st->n_grad, 3 * (int64_t)p->sh_L.size(), grad_centers,
+                           grad_exps);
         if (hipGetLastError() != hipSuccess) rc = ERI_EHIP;
     }
     if (rc == ERI_OK && energy) {

@@ -308,6 +308,97 @@ ERI_DEV void eri_pack_group(const void* stage, int n, int nq, int bits, int per,
     }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint contraction inside a derived-class kernel.  d/dA_x of a Cartesian
+// Gaussian is 2 alpha g_(a+1_x) - a_x g_(a-1_x) and d/dalpha of N g_a is
+// N [(3/4 + L/2)/alpha g_a - sum_x g_(a+2_x)]; the launch's derived shells
+// carry the factors of one term (2 alpha, the N ratios, (3/4 + L/2)/alpha),
+// so each derived ERI enters the gradient as
+//   grad[axis] += f * Gbar(user ERI o) * (derived ERI)
+// for the (o, axis, f) entries of its map (PLUS: o = a'-1_x, axis x, f = 1;
+// MINUS: o = a'+1_x, axis x, f = -(a'_x + 1); exponent kinds: axis 0,
+// f = 1, o = a' or a'-2_x).  Gbar comes as rows of dL/dERI per user quartet
+// (the caller's, or D_ab D_cd written for the pass).
+// ---------------------------------------------------------------------------
+struct eri_adj_quartet {
+    const double* g;   // Gbar row of the user quartet
+    int32_t sh[4];     // user shells
+    double w;          // degeneracy weight
+    int64_t i;         // user item
+    int32_t k;         // primitive of the differentiated shell (exponent kinds)
+};
+
+ERI_DEV void eri_adj_begin(const eri_adj_ctx& C, int64_t j, eri_adj_quartet& q)
+{
+    q.i = C.origin ? (int64_t)(C.origin[j] & 0xffffff) : j;
+    q.k = C.origin ? (C.origin[j] >> 24) : 0;
+    const eri_item u = C.uitems[q.i];
+    const int32_t p1 = u.bra & 0x7fffffff, p2 = u.ket & 0x7fffffff;
+    const eri_shell_pair P1 = C.pairs[p1], P2 = C.pairs[p2];
+    q.sh[0] = u.bra < 0 ? P1.sb : P1.sa;
+    q.sh[1] = u.bra < 0 ? P1.sa : P1.sb;
+    q.sh[2] = u.ket < 0 ? P2.sb : P2.sa;
+    q.sh[3] = u.ket < 0 ? P2.sa : P2.sb;
+    q.w = 1.0;
+    if (C.degen) {
+        if (q.sh[0] != q.sh[1]) q.w *= 2.0;
+        if (q.sh[2] != q.sh[3]) q.w *= 2.0;
+        if (p1 != p2) q.w *= 2.0;
+    }
+    q.g = C.gbar + C.g_base + (C.orig ? (int64_t)C.orig[q.i] : q.i) * C.n_eriq;
+}
+
+// Branch-free, so that the loads of many outputs can be in flight together:
+// the three map entries in one 16-byte load, an unused entry (-1) reads
+// Gbar[0] and counts 0.
+ERI_DEV void eri_adj_add(const eri_adj_ctx& C, const eri_adj_quartet& q, int idx, double x, double& g0, double& g1,
+                         double& g2)
+{
+    const int4 m = reinterpret_cast<const int4*>(C.map)[idx];
+    const int32_t v[3] = {m.x, m.y, m.z};
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+        const int32_t u = v[e] < 0 ? 0 : v[e];
+        const int f = (u >> 25) & 3;
+        const double fac = v[e] < 0 ? 0.0 : (f ? -(double)f : 1.0);
+        const double t = fac * q.g[u & 0x7ff] * x;
+        const int ax = (u >> 23) & 3;
+        g0 += ax == 0 ? t : 0.0;
+        g1 += ax == 1 ? t : 0.0;
+        g2 += ax == 2 ? t : 0.0;
+    }
+}
+
+// One thread per quartet: the quartet's sums (g0, g1, g2 over the axes) into
+// L's per-item buffer or the workgroup's gradient slice (the derivative for
+// the fourth centre follows from translation invariance: dA + dB + dC + dD
+// = 0).  Slices spread the FP64 atomics of quartets that share a shell over
+// many addresses.
+ERI_DEV void eri_adj_finish(const eri_adj_ctx& C, int64_t j, const eri_adj_quartet& q, double g0, double g1,
+                            double g2)
+{
+    g0 *= q.w;
+    g1 *= q.w;
+    g2 *= q.w;
+    if (C.kind < 0) {
+        C.eitem[j] = g0;
+        return;
+    }
+    double* slice = C.grad + (int64_t)(blockIdx.x % (unsigned)C.n_slices) * C.slice_stride;
+    if (C.kind <= 1) {
+        double* a = slice + 3 * (int64_t)q.sh[C.pos];
+        double* d = slice + 3 * (int64_t)q.sh[3];
+        atomicAdd(a, g0);
+        atomicAdd(a + 1, g1);
+        atomicAdd(a + 2, g2);
+        atomicAdd(d, -g0);
+        atomicAdd(d + 1, -g1);
+        atomicAdd(d + 2, -g2);
+    } else {
+        atomicAdd(slice + C.ns3 + C.poff[q.sh[C.pos]] + q.k, g0);
+    }
+}
+
 ERI_DEV void eri_store_code(void* codes, int64_t idx, int bytes, int q)
 {
     if (bytes == 2)

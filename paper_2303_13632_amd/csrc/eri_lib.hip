@@ -647,6 +647,7 @@ extern "C" int eri_plan_quartets(const eri_plan* p, int32_t class_id, int64_t fi
 
 static void fill_args(eri_plan* p, int c, eri_class_args& a, double* out_eri, void* out_codes, double* out_scales)
 {
+    a.adj = eri_adj_ctx{};
     a.pairs = p->d_pairs;
     a.prims = p->d_prims;
     a.out_eri = out_eri ? out_eri + p->class_eoff[c] : nullptr;

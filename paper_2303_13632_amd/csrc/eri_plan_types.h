@@ -33,6 +33,33 @@ struct eri_item {
     int32_t ket;
 };
 
+// Contraction of a derived-class launch of the adjoint: each derived ERI is
+// multiplied into dL/dERI of the user quartet it derives from, and the
+// per-quartet sums go to the gradients (map == null: a plain launch).
+struct eri_adj_ctx {
+    const int32_t* map;          // per derived ERI (user layout of its class): 4 slots (16-byte aligned), unused -1; an
+                                 // entry is o | axis << 23 | f << 25 with o the user ERI and factor +1
+                                 // (f = 0) or -f
+    const eri_item* uitems;      // user items of the pass
+    const int32_t* origin;       // derived item -> user item | primitive << 24 (exponent kinds), or null
+    const int32_t* orig;         // user item -> its Gbar row, or null: row = user item
+    const eri_shell_pair* pairs;
+    const double* gbar;          // dL/dERI, rows of n_eriq
+    int64_t g_base;              // index in gbar of row 0
+    const int64_t* poff;         // first primitive of each shell
+    double* grad;                // gradient slices: slice b at grad + b * slice_stride holds
+                                 // [n_shells][3] centre entries, then one entry per primitive
+    int64_t slice_stride;
+    int64_t ns3;                 // 3 n_shells
+    int32_t n_slices;            // workgroup w adds into slice w mod n_slices
+    int32_t pad;
+    double* eitem;               // base kind: per-item contribution to L
+    int32_t n_eriq;              // ERIs of a user quartet
+    int32_t kind;                // -1 base, 0 L+1, 1 L-1, 2 exponent (L), 3 exponent (L+2)
+    int32_t pos;                 // differentiated user position
+    int32_t degen;               // weight each quartet by its degeneracy in the full sum
+};
+
 // Arguments of every class kernel (by value).
 struct eri_class_args {
     const eri_item* items;          // the class's quartets in plan order
@@ -51,4 +78,5 @@ struct eri_class_args {
     int32_t pack_bits;              // > 0: out_codes is the packed stream of pack_bits-bit codes
     int32_t pack_per;               // floor(512 / pack_bits) codes per 64-byte word
     int64_t pack_wpq;               // words per quartet
+    eri_adj_ctx adj;                // adjoint contraction instead of stores (adj.map != null)
 };
