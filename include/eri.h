@@ -267,11 +267,17 @@ int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_
  * Derivatives follow from the differentiated Gaussians (centre: 2 alpha
  * g(a+1) - a g(a-1); exponent: N[(3/4 + L/2)/alpha g(a) - sum g(a+2)]) as
  * contracted ERIs of derived shells computed by the FP64 class kernels,
- * whatever the plan's precision; the fourth centre's derivative follows from
- * translation invariance.  Gradient accumulation uses FP64 atomics, so the
- * summation order (and the last bits of the gradients) may vary between
- * calls; L is summed in a fixed order with compensated (two-sum) arithmetic,
- * so *energy is the same on every call with the same inputs.
+ * whatever the plan's precision, which multiply each derived ERI into Gbar
+ * as it is produced (no derived integral is stored); the fourth centre's
+ * derivative follows from translation invariance.  Gradient accumulation
+ * uses FP64 atomics (one per quartet and axis, into one of up to 1024
+ * slices that a last kernel adds up in order), so the summation order (and
+ * the last bits of the gradients) may vary between calls; L is summed in a
+ * fixed order with compensated (two-sum) arithmetic, so *energy is the same
+ * on every call with the same inputs.  Device memory held for it: the
+ * derived pair tables, item buffers of up to 2^22 quartets per pass, the
+ * contraction maps, the slices (at most 128 MB) and, for a density, up to
+ * 1 GiB of D_ab D_cd rows per pass.
  * Returns ERI_EUNSUPPORTED when a shell of the plan has L > 2 (the exponent
  * derivative of an L shell needs L+2 integrals, computed up to g),
  * ERI_ESTATE for dl_deri with a plan whose output ring holds fewer quartets
