@@ -75,8 +75,12 @@ def cpu_baseline(classes, seconds, per_class_out=""):
                 per[cid] = int(sizes.sum()) / dt / 1e9
         return tot_t, tot_e, tot_q
 
-    t, neri, nq = run(1, threads)
-    n = max(4, min(8192, int(seconds / max(t, 1e-3))))
+    # quartets per class for about `seconds`: the cost per quartet from runs
+    # with 1 and 8 quartets per class (their difference drops the fixed cost)
+    t1, _, _ = run(1, threads)
+    t8, _, _ = run(8, threads)
+    per_q = max((t8 - t1) / 7.0, 1e-6)
+    n = max(8, min(8192, int(seconds / per_q)))
     per = {}
     t, neri, nq = run(n, threads, per)
     n1 = max(1, n // (2 * threads))
@@ -109,11 +113,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variants (no autotuning)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices")
-    ap.add_argument("--secondary", default="mixed,int12,fp64_out,int8,int32,gradient",
+    ap.add_argument("--secondary", default="mixed,int12,fp64_out,int8,int32,gradient,molecule",
                     help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
                          "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
                          "fp64_out / int8 / int32 (same workload with FP64 output or 8-/32-bit codes), "
-                         "gradient (fwd+grad on the 64-atom basis); 'none' for the headline only")
+                         "gradient (fwd+grad on the 64-atom basis), molecule (every screened quartet of the "
+                         "384-atom molecule-like basis in one graph launch); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy", "lattice"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
@@ -190,6 +195,16 @@ def main():
                                                           "forward_geris", "adjoint_geris")}
         out["secondary"]["fwd_grad"]["workload"] = g["config"]["workload"]
         out["secondary"]["fwd_grad"]["n_eri"] = g["config"]["n_eri"]
+    if "molecule" in sec:
+        import copy
+        margs = copy.copy(args)
+        margs.steps, margs.warmup = 1, 1
+        mol = bench_molecule(margs)
+        out["secondary"]["molecule"] = {k: mol[k] for k in ("value", "unit", "ms_per_step", "dtype")}
+        out["secondary"]["molecule"].update({k: mol["config"][k] for k in ("workload", "n_quartets", "n_eri")})
+        for k in ("tune_s", "plan_s", "whole_step_tflops"):
+            if k in mol:
+                out["secondary"]["molecule"][k] = mol[k]
     print(json.dumps(out), flush=True)
 
 
@@ -466,6 +481,7 @@ def bench_molecule(args):
     t0 = time.time()
     plan = eri.Plan(sh, None, precision=args.precision, bits=args.bits, schwarz=args.schwarz,
                     ring_bytes=int(args.ring_gb * 1e9))
+    plan_s = time.time() - t0
     log("plan: %d atoms, %d shells, %d screened quartets, %d ERIs, %d primitive quartets (%.1fs)"
         % (n_heavy + n_h, len(sh["L"]), plan.n_quartets, plan.n_eri, plan.n_prim_quartets, time.time() - t0))
     tune_s = 0.0
@@ -502,6 +518,7 @@ def bench_molecule(args):
                    "n_shells": int(len(sh["L"])), "n_quartets": int(plan.n_quartets),
                    "n_eri": int(plan.n_eri), "n_prim_quartets": int(plan.n_prim_quartets)},
         "whole_step_tflops": flops / (ms_step / 1e3) / 1e12, "tuned": not args.no_tune, "tune_s": tune_s,
+        "plan_s": plan_s,
     }
     return out
 
