@@ -282,7 +282,47 @@ def bench_packed(args, classes, bits):
     del vals, host_words, words, scales
     plan.close()
     torch.cuda.empty_cache()
+    res["decompression_error"] = packed_error_sample(classes, (bits, 16), 256)
     return res
+
+
+def packed_error_sample(classes, bits_list, nq):
+    """Largest decompression error of the packed stream on nq quartets per
+    class (same generator): plans writing the FP64 values and the packed
+    stream together, the stream decoded on the host (eq. 11) and compared
+    with the values, per width; also the largest error in units of half a
+    quantisation step (at most 1 by eq. 10)."""
+    import torch
+    from paper_2303_13632_amd import eri
+    shells, quartets = build_workload(nq, classes)
+    out = {"sample": "%d quartets of each class, FP64 values and the packed stream of the same plan" % nq}
+    for b in bits_list:
+        plan = eri.Plan(shells, quartets, precision="fp64", bits=b, device=0, packed=True)
+        e, words, scales = plan.alloc(eri=True, codes=True)
+        plan.compute(e, words, scales)
+        torch.cuda.synchronize()
+        off = []
+        for c in range(256):
+            n = int(plan.class_quartets[c])
+            if n:
+                m = int((plan.class_eri_off[c + 1] - plan.class_eri_off[c]) // n)
+                off.append(plan.class_eri_off[c] + m * np.arange(n))
+        off = np.concatenate(off + [np.array([plan.n_eri], dtype=np.int64)])
+        woff = eri.packed_word_offsets(b, off)
+        sc = scales.cpu().numpy()[: plan.n_quartets]
+        _, v = eri.unpack_host(b, words[: 8 * int(woff[-1])].cpu().numpy(), off, woff, scales=sc, codes=False,
+                               values=True)
+        x = e.cpu().numpy()[: plan.n_eri]
+        err = np.abs(v - x)
+        step = np.repeat(sc, np.diff(off))
+        m = step > 0
+        out["bits%d" % b] = {"max_abs_Ha": float(err.max()),
+                             "max_over_half_step": float((err[m] / (step[m] / 2)).max()) if m.any() else 0.0,
+                             "non_finite": int((~np.isfinite(v)).sum() + (~np.isfinite(x)).sum())}
+        del e, words, scales
+        plan.close()
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
