@@ -28,7 +28,7 @@ METRIC = "GERIS (1e9 ERIs/s) incl. int16 compression, FP64 vs FP32-mixed, + fwd+
 # MI355X vector peaks: FP64 78.6 TFLOP/s (published).  The published FP32 vector peak, 157.3 TFLOP/s,
 # counts packed FP32 instructions, which this build does not emit; unpacked FP32 issues at the FP64
 # rate, so FP32-mixed kernels are held to 78.6 as well.
-PEAK_TFLOPS = {"fp64": 78.6, "mixed": 78.6}
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 78.6, "rys": 78.6}
 
 
 def log(*a):
@@ -103,7 +103,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed", "rys"])
     ap.add_argument("--bits", type=int, default=16)
     ap.add_argument("--packed", action="store_true",
                     help="codes as the packed 512-bit word stream written by the kernels (ERI_PLAN_PACKED)")
@@ -113,12 +113,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch variants (no autotuning)")
     ap.add_argument("--tune-cache", default="", help="JSON cache of the autotuner's choices")
-    ap.add_argument("--secondary", default="mixed,int12,fp64_out,int8,int32,gradient,molecule",
+    ap.add_argument("--secondary", default="mixed,int12,fp64_out,int8,int32,gradient,molecule,rys",
                     help="extra measurements in the same line: mixed (FP32-mixed path on the same workload), "
                          "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
                          "fp64_out / int8 / int32 (same workload with FP64 output or 8-/32-bit codes), "
                          "gradient (fwd+grad on the 64-atom basis), molecule (every screened quartet of the "
-                         "384-atom molecule-like basis in one graph launch); 'none' for the headline only")
+                         "384-atom molecule-like basis in one graph launch), rys (the Rys-quadrature kernels "
+                         "against the Obara-Saika ones on the classes with L_tot <= 4); 'none' for the headline "
+                         "only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy", "lattice"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
@@ -205,7 +207,30 @@ def main():
         for k in ("tune_s", "plan_s", "whole_step_tflops"):
             if k in mol:
                 out["secondary"]["molecule"][k] = mol[k]
+    if "rys" in sec and args.precision == "fp64":
+        out["secondary"]["rys"] = bench_rys(args)
     print(json.dumps(out), flush=True)
+
+
+def bench_rys(args):
+    """The Rys-quadrature kernels (one lane per quartet, FP64) against the
+    Obara-Saika/HGP kernels on the classes with L_tot <= 4, same quartets,
+    both tuned, int16 codes: GERIS of each and the per-class time ratio."""
+    from paper_2303_13632_amd import workloads as W
+    classes = [c for c in range(256) if sum(W.class_of(c)) <= 4]
+    steps = max(1, args.steps // 2)
+    r = bench_classes(args, classes, "rys", args.bits, steps, 1, "")
+    o = bench_classes(args, classes, "fp64", args.bits, steps, 1, "")
+    ratio = {c: r["per_class_ms"][c] / o["per_class_ms"][c] for c in r["per_class_ms"]}
+    vals = sorted(ratio.values())
+    best = min(ratio, key=ratio.get)
+    return {"value": r["geris"], "unit": "GERIS", "os_value": o["geris"], "n_classes": len(classes),
+            "time_ratio_rys_over_os": {"min": vals[0], "median": vals[len(vals) // 2], "max": vals[-1],
+                                       "best_class": "[%d%d|%d%d]" % W.class_of(best)},
+            "roofline_class": r["roofline"]["class"], "roofline_frac": r["roofline"]["frac"],
+            "note": "classes with La+Lb+Lc+Ld <= 4, %d quartets each; the Rys FLOP count (node/weight series, "
+                    "2D recurrences and transfers per node, three products per ERI and node) is its own"
+                    % args.quartets_per_class}
 
 
 def measured_traffic(kernel):
@@ -406,6 +431,7 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
               "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
               "n_prim_quartets": int(plan.n_prim_quartets), "precision": precision, "bits": bits}
     res = {"geris": geris, "ms_per_step": ms_step, "config": config, "roofline": roof,
+           "per_class_ms": {c: float(per_class_ms[i]) for i, c in enumerate(active)},
            "n_fp32": int(plan.class_fp32[active].sum()),
            "whole_step_tflops": total_flops / (ms_step / 1e3) / 1e12, "active": active,
            "tuned": not args.no_tune, "tune_s": tune_s}

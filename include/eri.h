@@ -62,6 +62,12 @@ extern "C" {
 #define ERI_FP32_MIXED 1       /* VRR/HRR in FP32; Boys, prefactors, contraction in FP64 -- for
                                   the classes whose FP32 recurrences meet 1e-7 Ha with a tenfold
                                   margin (eri_plan_info.class_fp32); FP64 kernels for the rest */
+#define ERI_RYS 2              /* Rys quadrature (Sec. II-C, eqs. 5-8) in FP64, one lane per
+                                  quartet: nodes and weights of the Rys rule from tabulated fits
+                                  (relative error 2e-16), 2D integrals by the Rys recurrences,
+                                  transfer to B and D per axis.  Classes with La+Lb+Lc+Ld <= 4
+                                  only (plan creation returns ERI_EUNSUPPORTED for others and
+                                  for ERI_PLAN_ALL_QUARTETS plans) */
 
 typedef struct eri_plan eri_plan;
 
@@ -69,7 +75,7 @@ typedef struct eri_plan eri_plan;
 #define ERI_PLAN_PACKED 2        /* codes written as the packed 512-bit word stream (see eri_compute) */
 
 typedef struct {
-    int32_t precision;          /* ERI_FP64 or ERI_FP32_MIXED */
+    int32_t precision;          /* ERI_FP64, ERI_FP32_MIXED or ERI_RYS */
     int32_t bits;               /* code width n of eq. 10: 0 = no codes, else 2..32 */
     int32_t device;             /* HIP device ordinal */
     int32_t flags;              /* ERI_PLAN_ALL_QUARTETS and/or ERI_PLAN_PACKED, or 0 */

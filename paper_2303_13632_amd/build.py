@@ -54,16 +54,28 @@ def _compile(src, obj, deps):
     return obj, time.time() - t0, True
 
 
-def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=None):
+def build(jobs=None, verbose=True, precisions=("fp64", "mixed", "rys"), classes=None):
     sys.path.insert(0, CSRC)
     import codegen  # noqa: E402
     import gen_boys_table  # noqa: E402
+    import gen_rys_table  # noqa: E402
     sys.path.pop(0)
     os.makedirs(GEN, exist_ok=True)
     os.makedirs(OBJ, exist_ok=True)
     bt = os.path.join(GEN, "boys_table.h")
     if not os.path.exists(bt):
         gen_boys_table.write(bt)
+    # the Rys rule's tables (about 30 s of 40-digit arithmetic): rewritten when
+    # their generator changes
+    rt = os.path.join(GEN, "rys_table.h")
+    rstamp = rt + ".sha"
+    rdig = _digest([os.path.join(CSRC, "gen_rys_table.py")])
+    if "rys" in precisions and not (os.path.exists(rt) and os.path.exists(rstamp) and open(rstamp).read() == rdig):
+        err = gen_rys_table.write(rt)
+        with open(rstamp, "w") as f:
+            f.write(rdig)
+        if verbose:
+            print("  Rys rule tables: max relative error %.2e" % err, flush=True)
     files, _ = codegen.generate(GEN, precisions=precisions, classes=classes)
     # generated kernel TUs see the device headers only; the host TUs also the
     # plan internals and the C ABI header
@@ -76,9 +88,11 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed"), classes=None):
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         futs = {}
+        rdeps = kdeps + [os.path.join(CSRC, "eri_rys.h"), os.path.join(GEN, "rys_table.h")]
         for s in srcs:
             obj = os.path.join(OBJ, os.path.basename(s) + ".o")
-            futs[ex.submit(_compile, s, obj, hdeps if s in host else kdeps)] = s
+            deps = hdeps if s in host else (rdeps if os.path.basename(s) == "eri_rys.hip" else kdeps)
+            futs[ex.submit(_compile, s, obj, deps)] = s
         for fu in cf.as_completed(futs):
             obj, dt, did = fu.result()
             objs.append(obj)

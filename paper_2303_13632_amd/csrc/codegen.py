@@ -33,7 +33,7 @@ import itertools
 import math
 import os
 
-REALS = {"fp64": "double", "mixed": "float"}
+REALS = {"fp64": "double", "mixed": "float", "rys": "double"}
 
 # kernel name -> 1 if its packed-stream path stages codes in dynamic LDS (sized
 # at launch), 0 if in the kernel's own LDS once the HRR staging is consumed
@@ -439,6 +439,134 @@ def emit_mode_T(cp, prec, name):
     emit_store_T(em, cp, outs, prec)
     em.end()
     return name, em.text()
+
+
+RYS_LMAX = 4      # classes with L_tot <= 4 get a Rys-quadrature kernel (at most 3 roots)
+
+
+def emit_mode_R(cp, name):
+    """Rys-quadrature kernel of a class (Sec. II-C, eqs. 5-8), one lane per
+    quartet, FP64, in the orientation cp.perm of the Obara-Saika kernels.
+    Per primitive quartet the n = L_tot/2 + 1 nodes x_r = t_r^2 and weights
+    w_r of the Rys rule at T come from the tabulated fits (eri_rys_rule);
+    per node and axis the 2D integrals G(n, m), n <= L_a + L_b, m <= L_c + L_d,
+    follow the Rys recurrences
+        G(n+1, 0) = C00 G(n, 0) + n B10 G(n-1, 0)
+        G(n, m+1) = C00' G(n, m) + m B01 G(n, m-1) + n B00 G(n-1, m)
+    with B00 = x/(2(p+q)), B10 = (1 - q x/(p+q))/(2p), B01 = (1 - p x/(p+q))/(2q),
+    C00 = (P-A) + x (W-P), C00' = (Q-C) + x (W-Q), G(0, 0) = 1 for x and y and
+    the weight times the prefactor for z; the horizontal transfer moves
+    angular momentum to B and D per axis (I(a, b+1) = I(a+1, b) + (A-B) I(a,
+    b)); each ERI adds sum_r Ix Iy Iz.  Returns (name, source, FLOPs per
+    primitive quartet)."""
+    a, b, c, d = cp.a, cp.b, cp.c, cp.d
+    Lab, Lcd = a + b, c + d
+    N = cp.Ltot // 2 + 1
+    em = Emitter()
+    flops = [30 + 2 * N * 3 * 14 + 4 * N]      # setup, the node/weight series, their scaling
+
+    def count(expr):
+        flops[0] += expr.count("*") + expr.count(" + ") + expr.count(" - ")
+    em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], Rys quadrature (%d nodes), one lane per quartet"
+       % (cp.user + (cp.perm, a, b, c, d, N)))
+    em("__global__ __launch_bounds__(256) void %s(eri_class_args A)" % name)
+    em.block("")
+    em("const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;")
+    em("if (t >= A.n_items) return;")
+    em("const eri_item it = A.items[t];")
+    em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
+    em("const eri_shell_pair BP = A.pairs[it.bra & 0x7fffffff];")
+    em("const eri_shell_pair KP = A.pairs[it.ket & 0x7fffffff];")
+    ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
+    outs = []
+    for ia, ai in enumerate(ca):
+        for ib_, bi in enumerate(cb):
+            for ic, ci in enumerate(cc):
+                for id_, di in enumerate(cd):
+                    outs.append(("o%d" % len(outs), (ia, ib_, ic, id_), (ai, bi, ci, di)))
+    for nm, _, _ in outs:
+        em("double %s = 0.0;" % nm)
+    em.block("for (int ib = 0; ib < BP.nprim; ++ib)")
+    em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
+    em.block("for (int ik = 0; ik < KP.nprim; ++ik)")
+    em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
+    em("eri_pq_fp64 S;")
+    em("eri_pq_setup(B, K, S);")
+    em("double rx[%d], rw[%d];" % (N, N))
+    em("eri_rys_rule<%d>(S.T, rx, rw);" % N)
+    em("#pragma unroll")
+    em.block("for (int r = 0; r < %d; ++r)" % N)
+    em("const double u = rx[r];")
+    em("const double B00 = u * S.hpq;")
+    em("const double B10 = B.hp - B.hp * S.rho_p * u;")
+    em("const double B01 = K.hp - K.hp * S.rho_q * u;")
+    flops[0] += 5
+    defined = set()
+
+    def g(ax, n, m):
+        nm = "g%s_%d_%d" % (ax, n, m)
+        if nm in defined:
+            return nm
+        i = "xyz".index(ax)
+        if n == 0 and m == 0:
+            expr = "rw[r] * S.pref" if ax == "z" else "1.0"
+        elif m == 0:
+            expr = "C0%s * %s" % (ax, g(ax, n - 1, 0))
+            if n - 1 >= 1:
+                expr += " + %s * B10 * %s" % (lit(n - 1), g(ax, n - 2, 0))
+        else:
+            expr = "D0%s * %s" % (ax, g(ax, n, m - 1))
+            if m - 1 >= 1:
+                expr += " + %s * B01 * %s" % (lit(m - 1), g(ax, n, m - 2))
+            if n >= 1:
+                expr += " + %s * B00 * %s" % (lit(n), g(ax, n - 1, m - 1))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+
+    def kh(ax, n, cx, dx):
+        # ket transfer: K(n, c, d+1) = K(n, c+1, d) + (C-D) K(n, c, d); K(n, c, 0) = G(n, c)
+        if dx == 0:
+            return g(ax, n, cx)
+        nm = "k%s_%d_%d_%d" % (ax, n, cx, dx)
+        if nm in defined:
+            return nm
+        expr = "%s + CD%s * %s" % (kh(ax, n, cx + 1, dx - 1), ax, kh(ax, n, cx, dx - 1))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+
+    def ih(ax, ax_a, bx, cx, dx):
+        # bra transfer: I(a, b+1) = I(a+1, b) + (A-B) I(a, b); I(a, 0) = K(a)
+        if bx == 0:
+            return kh(ax, ax_a, cx, dx)
+        nm = "i%s_%d_%d_%d_%d" % (ax, ax_a, bx, cx, dx)
+        if nm in defined:
+            return nm
+        expr = "%s + AB%s * %s" % (ih(ax, ax_a + 1, bx - 1, cx, dx), ax, ih(ax, ax_a, bx - 1, cx, dx))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+    for i, ax in enumerate("xyz"):
+        em("const double C0%s = B.PA[%d] + u * S.WP[%d];" % (ax, i, i))
+        em("const double D0%s = K.PA[%d] + u * S.WQ[%d];" % (ax, i, i))
+        em("const double AB%s = BP.AB[%d], CD%s = KP.AB[%d];" % (ax, i, ax, i))
+        flops[0] += 4
+    for nm, _, (ai, bi, ci, di) in outs:
+        fx = ih("x", ai[0], bi[0], ci[0], di[0])
+        fy = ih("y", ai[1], bi[1], ci[1], di[1])
+        fz = ih("z", ai[2], bi[2], ci[2], di[2])
+        em("%s += %s * %s * %s;" % (nm, fx, fy, fz))
+        flops[0] += 3
+    em.end()
+    em.end()
+    em.end()
+    emit_store_T(em, cp, [(nm, ix) for nm, ix, _ in outs], "rys")
+    em.end()
+    return name, em.text(), flops[0]
 
 
 def user_strides(cp):
@@ -1548,7 +1676,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     if classes is None:
         classes = [class_of(c) for c in range(256)]
     fp32_ok = mixed_fp32_classes()
-    jobs = [(c, prec) for prec in precisions for c in classes
+    jobs = [(c, prec) for prec in precisions if prec != "rys" for c in classes
             if prec != "mixed" or class_id(*c) in fp32_ok]
     if g_classes:
         jobs += [(c, "fp64") for c in G_CLASSES]
@@ -1629,11 +1757,38 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
         fn = os.path.join(outdir, "eri_k%03d.hip" % (g // group))
         write_if_changed(fn, "\n".join(parts))
         files.append(fn)
+    if "rys" in precisions:
+        # Rys-quadrature kernels (classes with L_tot <= RYS_LMAX): one TU that
+        # alone includes the tables of the Rys rule
+        parts = [HEADER, '#include "eri_rys.h"', '#include "eri_dispatch.h"']
+        lines_ = []
+        for user in classes:
+            if sum(user) > RYS_LMAX:
+                continue
+            cp = plans.get(user) or ClassPlan(*user, **overrides.get(user, {}))
+            plans[user] = cp
+            name = kernel_name("rys", cp.user)
+            _, src, fpq = emit_mode_R(cp, name)
+            parts.append(src)
+            pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
+            c5 = class_id5(*user)
+            for k, blk in enumerate((64, 128, 256)):
+                info = "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, %d, 0, 1}" % (
+                    name, blk, blk, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, TAG_DEFAULT)
+                if k == 0:
+                    lines_.append("    t[%d] = %s;" % (c5, info))
+                lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
+        parts.append("void eri_register_rys(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % "\n".join(lines_))
+        fn = os.path.join(outdir, "eri_rys.hip")
+        write_if_changed(fn, "\n".join(parts))
+        files.append(fn)
+        regs.append(("rys", "eri_register_rys"))
     lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
     for prec, fname in regs:
         lines.append("void %s(eri_kernel_info* t, eri_kernel_info* v);" % fname)
-    lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5];")
-    lines.append("static eri_kernel_info v_fp64[ERI_NCLASS5 * ERI_MAXVAR], v_mixed[ERI_NCLASS5 * ERI_MAXVAR];")
+    lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5], g_rys[ERI_NCLASS5];")
+    lines.append("static eri_kernel_info v_fp64[ERI_NCLASS5 * ERI_MAXVAR], v_mixed[ERI_NCLASS5 * ERI_MAXVAR],")
+    lines.append("    v_rys[ERI_NCLASS5 * ERI_MAXVAR];")
     lines.append("static std::once_flag g_once;")
     routed = [class_id5(*c) for c in classes if class_id(*c) not in fp32_ok] if "mixed" in precisions else []
     lines.append("// classes whose FP32-mixed entries are their FP64 kernels")
@@ -1642,7 +1797,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     lines.append("{")
     lines.append("    std::call_once(g_once, [] {")
     for prec, fname in regs:
-        lines.append("        %s(%s);" % (fname, "g_fp64, v_fp64" if prec == "fp64" else "g_mixed, v_mixed"))
+        lines.append("        %s(g_%s, v_%s);" % (fname, prec, prec))
     lines.append("        for (int c5 : g_mixed_fp64) {")
     lines.append("            if (c5 < 0) continue;")
     lines.append("            g_mixed[c5] = g_fp64[c5];")
@@ -1653,12 +1808,12 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
     lines.append("{")
     lines.append("    fill();")
-    lines.append("    return precision == 1 ? g_mixed : g_fp64;")
+    lines.append("    return precision == 2 ? g_rys : precision == 1 ? g_mixed : g_fp64;")
     lines.append("}")
     lines.append("const eri_kernel_info* eri_kernel_variants(int precision)")
     lines.append("{")
     lines.append("    fill();")
-    lines.append("    return precision == 1 ? v_mixed : v_fp64;")
+    lines.append("    return precision == 2 ? v_rys : precision == 1 ? v_mixed : v_fp64;")
     lines.append("}")
     fn = os.path.join(outdir, "eri_dispatch_table.hip")
     write_if_changed(fn, "\n".join(lines) + "\n")

@@ -19,7 +19,7 @@ struct eri_kernel_info {
     int32_t pack_dyn;    // packed stream stages codes in dynamic LDS: 0 never, 1 always, 2 for n > 16
 };
 
-// Kernel table of a precision (0: FP64, 1: FP32-mixed), indexed by
+// Kernel table of a precision (0: FP64, 1: FP32-mixed, 2: Rys quadrature), indexed by
 // La*125 + Lb*25 + Lc*5 + Ld (angular momenta up to 4); entries of classes
 // without a kernel have fn == nullptr.  The FP32-mixed table holds FP64
 // kernels (fp32 == 0) for the classes whose FP32 recurrences miss 1e-7 Ha.

@@ -112,9 +112,15 @@ void build_pair_tables(const shell_set& s, const std::vector<uint64_t>& keys, st
 }
 
 
+// Index of a precision's kernel tables (0 FP64, 1 FP32-mixed, 2 Rys).
+static int table_index(int precision)
+{
+    return precision == ERI_RYS ? 2 : precision == ERI_FP32_MIXED ? 1 : 0;
+}
+
 const eri_kernel_info* kernel_table(int precision)
 {
-    return eri_kernel_table(precision == ERI_FP32_MIXED ? 1 : 0);
+    return eri_kernel_table(table_index(precision));
 }
 
 int upload(eri_plan* p, void** dst, const void* src, size_t bytes)
@@ -489,7 +495,9 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     const shell_set s{n_shells, L, K, xyz, prim_off, exps, coefs};
     int rc = check_shells(s);
     if (rc) return rc;
-    if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED) return ERI_EUNSUPPORTED;
+    if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED && opts->precision != ERI_RYS)
+        return ERI_EUNSUPPORTED;
+    if (opts->precision == ERI_RYS && (opts->flags & ERI_PLAN_ALL_QUARTETS)) return ERI_EUNSUPPORTED;
     if (opts->bits != 0 && (opts->bits < 2 || opts->bits > 32)) return ERI_EUNSUPPORTED;
     if (!(opts->schwarz_threshold >= 0.0) || opts->ring_bytes < 0 || opts->chunk_quartets < 0 ||
         opts->scale_block < 0)
@@ -588,7 +596,7 @@ extern "C" int eri_plan_info_get(const eri_plan* p, eri_plan_info* info)
         info->class_mode[c] = ki.mode;
         info->class_block[c] = ki.block;
         info->class_per_block[c] = ki.per_block;
-        const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
+        const eri_kernel_info* var = eri_kernel_variants(table_index(p->precision));
         int nv = 0;
         while (nv < ERI_MAXVAR && var[class_id5_of(c) * ERI_MAXVAR + nv].fn) ++nv;
         info->class_n_variants[c] = nv;
@@ -722,7 +730,7 @@ static const eri_kernel_info& class_kernel(const eri_plan* p, int c)
 {
     const int c5 = class_id5_of(c);
     if (p->class_var[c] > 0) {
-        const eri_kernel_info& v = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0)[c5 * ERI_MAXVAR + p->class_var[c]];
+        const eri_kernel_info& v = eri_kernel_variants(table_index(p->precision))[c5 * ERI_MAXVAR + p->class_var[c]];
         if (v.fn) return v;
     }
     return kernel_table(p->precision)[c5];
@@ -934,7 +942,7 @@ extern "C" int eri_compute_class(eri_plan* p, int32_t c, void* stream, double* o
 static std::string tune_key(const eri_plan* p, int c)
 {
     char buf[64];
-    std::snprintf(buf, sizeof(buf), "%s:%d:%d", p->precision == ERI_FP32_MIXED ? "mixed" : "fp64", c, p->bits);
+    std::snprintf(buf, sizeof(buf), "%s:%d:%d", p->precision == ERI_RYS ? "rys" : p->precision == ERI_FP32_MIXED ? "mixed" : "fp64", c, p->bits);
     return buf;
 }
 
@@ -977,7 +985,7 @@ static bool write_tune_cache(const char* path, const std::map<std::string, int>&
 
 static int tune_plan(eri_plan* p, hipStream_t st, int64_t sample, int trials, const char* cache_path)
 {
-    const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
+    const eri_kernel_info* var = eri_kernel_variants(table_index(p->precision));
     std::map<std::string, int> cache;
     if (cache_path) read_tune_cache(cache_path, cache);
     // sample sizes and scratch outputs
@@ -1117,9 +1125,13 @@ extern "C" int eri_plan_tune(eri_plan* p, void* stream, int64_t sample_quartets,
 extern "C" int eri_plan_set_variants(eri_plan* p, const int32_t* v)
 {
     if (!p || !v) return ERI_EINVAL;
-    const eri_kernel_info* var = eri_kernel_variants(p->precision == ERI_FP32_MIXED ? 1 : 0);
-    for (int c = 0; c < 256; ++c)
-        if (v[c] < 0 || v[c] >= ERI_MAXVAR || !var[class_id5_of(c) * ERI_MAXVAR + v[c]].fn) return ERI_EINVAL;
+    const eri_kernel_info* var = eri_kernel_variants(table_index(p->precision));
+    // a class without quartets in the plan may keep variant 0 even where its
+    // precision has no kernel (the Rys family covers L_tot <= 4 only)
+    for (int c = 0; c < 256; ++c) {
+        if (v[c] < 0 || v[c] >= ERI_MAXVAR) return ERI_EINVAL;
+        if (!var[class_id5_of(c) * ERI_MAXVAR + v[c]].fn && (v[c] != 0 || p->class_count[c])) return ERI_EINVAL;
+    }
     for (int c = 0; c < 256; ++c) p->class_var[c] = v[c];
     if (p->graph) {
         (void)hipGraphExecDestroy(p->graph);

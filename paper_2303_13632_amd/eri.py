@@ -21,7 +21,8 @@ ERI_EHIP = -4
 ERI_ESTATE = -5
 ERI_FP64 = 0
 ERI_FP32_MIXED = 1
-PRECISIONS = {"fp64": ERI_FP64, "mixed": ERI_FP32_MIXED}
+ERI_RYS = 2
+PRECISIONS = {"fp64": ERI_FP64, "mixed": ERI_FP32_MIXED, "rys": ERI_RYS}
 
 _lib = None
 
@@ -227,6 +228,8 @@ class Plan:
 
     def kernel_name(self, cid):
         """Name of the kernel a class launch uses (variant included)."""
+        if self.precision == "rys":
+            return "eri_rys_c%03d" % cid
         prec = "mixed" if self.class_fp32[cid] else "fp64"
         return "eri_%s_c%03d%s" % (prec, cid, KERNEL_TAG_SUFFIX[int(self.class_tag[cid])])
 

@@ -1,0 +1,65 @@
+"""GPU parity of the Rys-quadrature kernels (precision "rys": Sec. II-C,
+eqs. 5-8, for the classes with La+Lb+Lc+Ld <= 4) against the oracle: FP64
+ERIs within 1e-12 Ha (quartets that miss it against the double oracle are
+refereed by its __float128 build), fused codes and scales bit-identical to the
+oracle's compressor fed the GPU's doubles, every launch variant; and the
+classes and plan kinds the family does not cover are refused."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2303_13632_amd import workloads as W
+from parity_util import check_quartets
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+N_PER_CLASS = 67
+RYS_CLASSES = [c for c in range(256) if sum(W.class_of(c)) <= 4]
+
+
+def _blocks(sizes):
+    off = np.zeros(len(sizes) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(sizes)
+    return off
+
+
+def test_rys_classes_vs_oracle():
+    from paper_2303_13632_amd import eri
+    assert len(RYS_CLASSES) == 66
+    parts = [W.class_case(cid, n_quartets=N_PER_CLASS, seed=W.SEED_BASE + 95) for cid in RYS_CLASSES]
+    shells, quartets = W.merge(parts)
+    ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
+    plan = eri.Plan(shells, quartets, precision="rys", bits=16)
+    nv = plan.class_n_variants
+    sz = np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets)
+    blk = _blocks(sz)
+    for k in range(int(nv.max())):
+        print("variant pass %d" % k, flush=True)
+        plan.set_variants(np.where(nv > k, k, 0).astype(np.int32))
+        e, c, s = plan.alloc(eri=True, codes=True)
+        plan.compute(e, c, s)
+        torch.cuda.synchronize()
+        vals = e.cpu().numpy()[: plan.n_eri]
+        got = plan.to_user(vals)
+        err, nref = check_quartets(shells, quartets, got, ref, ref_off, sizes, THREADS)
+        print("variant %d: max |err| %.3e (%d refereed)" % (k, err, nref), flush=True)
+        oc, oe = O.compress(16, vals, blk)
+        assert np.array_equal(oe, s.cpu().numpy()[: plan.n_quartets]), k
+        assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32)), k
+        del e, c, s
+    assert plan.kernel_name(RYS_CLASSES[-1]).startswith("eri_rys_c")
+
+
+def test_rys_refusals():
+    from paper_2303_13632_amd import eri
+    # a class above L_tot = 4 has no Rys kernel
+    sh, q = W.class_case(W.class_id(2, 1, 1, 1), n_quartets=4)
+    with pytest.raises(eri.EriError):
+        eri.Plan(sh, q, precision="rys", bits=16)
+    # screened (all-quartet) plans are not offered in this precision
+    sh = W.molecule_basis(n_heavy=1, n_h=1, lattice=(2, 1, 1))
+    with pytest.raises(eri.EriError):
+        eri.Plan(sh, None, precision="rys", bits=16)
