@@ -63,3 +63,27 @@ def test_rys_refusals():
     sh = W.molecule_basis(n_heavy=1, n_h=1, lattice=(2, 1, 1))
     with pytest.raises(eri.EriError):
         eri.Plan(sh, None, precision="rys", bits=16)
+
+
+@pytest.mark.parametrize("bits,packed", [(8, False), (32, False), (12, True)])
+def test_rys_codes(bits, packed):
+    """Fused compression of the Rys kernels at other widths and into the
+    packed stream: bit-identical to the oracle's compressor (and packing) of
+    the GPU's doubles."""
+    from paper_2303_13632_amd import eri
+    parts = [W.class_case(cid, n_quartets=23, seed=W.SEED_BASE + 96) for cid in RYS_CLASSES]
+    shells, quartets = W.merge(parts)
+    plan = eri.Plan(shells, quartets, precision="rys", bits=bits, packed=packed)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    vals = e.cpu().numpy()[: plan.n_eri]
+    sz = np.repeat(np.diff(plan.class_eri_off) // np.maximum(plan.class_quartets, 1), plan.class_quartets)
+    blk = _blocks(sz)
+    oc, oe = O.compress(bits, vals, blk)
+    assert np.array_equal(oe, s.cpu().numpy()[: plan.n_quartets])
+    if packed:
+        ref, _ = O.pack(bits, oc, blk)
+        assert np.array_equal(c.cpu().numpy().view(np.uint8)[: len(ref)], ref)
+    else:
+        assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32))
