@@ -16,9 +16,9 @@ import os
 import sys
 
 NMAX = 4          # points: classes up to L_tot = 6
-H = 0.5           # interval width in T
+H = 0.25          # interval width in T
 TMAX = 64.0       # first T of the half-line rule
-DEG = 14          # Chebyshev degree per interval
+DEG = 8           # Chebyshev degree per interval
 
 
 def _mp():
