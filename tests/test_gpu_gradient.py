@@ -305,9 +305,9 @@ def test_multi_pass():
 
 
 def test_global_atomic_fallback():
-    """More gradient entries (3 per shell + one per primitive) than the
-    per-workgroup LDS copy holds: the contraction adds into the caller's
-    arrays with global atomics.  Against the oracle."""
+    """A large gradient (3 per shell + one per primitive, more than 4096
+    entries) over many slices: the per-quartet atomics land in the slice of
+    their workgroup and the slices are added in order.  Against the oracle."""
     from paper_2303_13632_amd import eri
     n = 1200
     sh = W.random_shells(n, lmax=2, seed=161, box=12.0)
