@@ -35,9 +35,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def build_workload(qpc, classes):
+def build_workload(qpc, classes, k_fixed=None):
     from paper_2303_13632_amd import workloads as W
-    parts = [W.class_case(cid, n_quartets=qpc) for cid in classes]
+    if k_fixed is None:
+        parts = [W.class_case(cid, n_quartets=qpc) for cid in classes]
+    else:
+        # same generator and seeds, every shell with k_fixed primitives
+        parts = [W.random_class_quartets(*W.class_of(cid), qpc, (W.SEED_BASE + 1) * 1000 + cid, k_fixed=k_fixed)
+                 for cid in classes]
     return W.merge(parts)
 
 
@@ -159,7 +164,7 @@ def main():
     out = {
         "metric": METRIC, "value": res["geris"], "unit": "GERIS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic",
         "config": res["config"],
         "whole_step_tflops": res["whole_step_tflops"],
@@ -213,24 +218,39 @@ def main():
 
 
 def bench_rys(args):
-    """The Rys-quadrature kernels (one lane per quartet, FP64) against the
-    Obara-Saika/HGP kernels on the classes with L_tot <= 4, same quartets,
-    both tuned, int16 codes: GERIS of each and the per-class time ratio."""
+    """The Rys-quadrature kernels (FP64; one lane per quartet for L_tot <= 4,
+    one workgroup per quartet above) against the Obara-Saika/HGP kernels on
+    the same quartets of every class, both tuned, int16 codes: GERIS of each
+    and the per-class time ratio, on the workload (K~U{1,2,3}) and with one
+    primitive per shell (K = 1, where the paper expects Rys to need fewer
+    operations for high angular momenta)."""
     from paper_2303_13632_amd import workloads as W
-    classes = [c for c in range(256) if sum(W.class_of(c)) <= 4]
+    classes = list(range(256))
     steps = max(1, args.steps // 2)
-    r = bench_classes(args, classes, "rys", args.bits, steps, 1, "")
-    o = bench_classes(args, classes, "fp64", args.bits, steps, 1, "")
-    ratio = {c: r["per_class_ms"][c] / o["per_class_ms"][c] for c in r["per_class_ms"]}
-    vals = sorted(ratio.values())
-    best = min(ratio, key=ratio.get)
-    return {"value": r["geris"], "unit": "GERIS", "os_value": o["geris"], "n_classes": len(classes),
-            "time_ratio_rys_over_os": {"min": vals[0], "median": vals[len(vals) // 2], "max": vals[-1],
-                                       "best_class": "[%d%d|%d%d]" % W.class_of(best)},
-            "roofline_class": r["roofline"]["class"], "roofline_frac": r["roofline"]["frac"],
-            "note": "classes with La+Lb+Lc+Ld <= 4, %d quartets each; the Rys FLOP count (node/weight series, "
-                    "2D recurrences and transfers per node, three products per ERI and node) is its own"
-                    % args.quartets_per_class}
+    out = {}
+    for key, kf in (("workload", None), ("k1", 1)):
+        r = bench_classes(args, classes, "rys", args.bits, steps, 1, "", k_fixed=kf)
+        o = bench_classes(args, classes, "fp64", args.bits, steps, 1, "", k_fixed=kf)
+        ratio = {c: r["per_class_ms"][c] / o["per_class_ms"][c] for c in r["per_class_ms"]}
+        vals = sorted(ratio.values())
+        by_l = {}
+        for c, v in ratio.items():
+            by_l.setdefault(sum(W.class_of(c)), []).append(v)
+        out[key] = {"value": r["geris"], "unit": "GERIS", "os_value": o["geris"], "n_classes": len(classes),
+                    "ms_per_step": r["ms_per_step"], "os_ms_per_step": o["ms_per_step"],
+                    "time_ratio_rys_over_os": {"min": vals[0], "median": vals[len(vals) // 2], "max": vals[-1],
+                                               "best_class": "[%d%d|%d%d]" % W.class_of(min(ratio, key=ratio.get)),
+                                               "median_by_L_tot": {str(k): float(np.median(v))
+                                                                   for k, v in sorted(by_l.items())}},
+                    "roofline_class": r["roofline"]["class"], "roofline_kernel": r["roofline"]["kernel"],
+                    "roofline_frac": r["roofline"]["frac"], "whole_step_tflops": r["whole_step_tflops"],
+                    "config": r["config"]["workload"]}
+    res = dict(out["workload"])
+    res["k1"] = out["k1"]
+    res["note"] = ("every class, %d quartets each; the Rys FLOP count (node/weight series, 2D recurrences "
+                   "and transfers per node and axis, three products per ERI and node) is its own"
+                   % args.quartets_per_class)
+    return res
 
 
 def measured_traffic(kernel):
@@ -350,14 +370,14 @@ def packed_error_sample(classes, bits_list, nq):
     return out
 
 
-def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
+def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out, k_fixed=None):
     """The 256-class workload: all classes once per step (HIP events around
     every class launch on the launch stream)."""
     import torch
     from paper_2303_13632_amd import eri
     from paper_2303_13632_amd import workloads as W
     t0 = time.time()
-    shells, quartets = build_workload(args.quartets_per_class, classes)
+    shells, quartets = build_workload(args.quartets_per_class, classes, k_fixed)
     log("workload: %d quartets, %d shells (%.1fs)" % (len(quartets), len(shells["L"]), time.time() - t0))
     t0 = time.time()
     packed = bool(getattr(args, "packed", False)) and bits > 0
@@ -423,9 +443,10 @@ def bench_classes(args, classes, precision, bits, steps, warmup, per_class_out):
                          "block": int(plan.class_block[c])})
         with open(per_class_out, "w") as f:
             json.dump(rows, f, indent=1)
-    config = {"workload": "%d classes x %d quartets, K~U{1,2,3}, centres U[0,10)^3 Bohr, exponents "
+    config = {"workload": "%d classes x %d quartets, %s, centres U[0,10)^3 Bohr, exponents "
                           "log-U[0.1,100], coefs U[0.1,1]; %s recurrences, %s"
-                          % (len(active), args.quartets_per_class, precision,
+                          % (len(active), args.quartets_per_class,
+                             "K~U{1,2,3}" if k_fixed is None else "K=%d" % k_fixed, precision,
                              ("int%d per-quartet compression" % bits + (", codes packed in 512-bit words" if packed else ""))
                              if bits else "FP64 output, no compression"),
               "n_eri": int(plan.n_eri), "n_quartets": int(plan.n_quartets),
@@ -576,7 +597,7 @@ def bench_molecule(args):
         "metric": METRIC, "value": geris, "unit": "GERIS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "wall_ms_per_step": wall * 1e3 / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": "molecule-like basis: %d heavy (s,s,s,p,p,d; K 1-6; exps log-U[0.1,5000]) + %d H "
                                "(s,s,p) atoms on a jittered 3.5 Bohr lattice; all unique quartets with "
                                "Q_ab Q_cd >= %g in one graph launch; int%d codes, %.0f GB output ring"

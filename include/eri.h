@@ -62,12 +62,13 @@ extern "C" {
 #define ERI_FP32_MIXED 1       /* VRR/HRR in FP32; Boys, prefactors, contraction in FP64 -- for
                                   the classes whose FP32 recurrences meet 1e-7 Ha with a tenfold
                                   margin (eri_plan_info.class_fp32); FP64 kernels for the rest */
-#define ERI_RYS 2              /* Rys quadrature (Sec. II-C, eqs. 5-8) in FP64, one lane per
-                                  quartet: nodes and weights of the Rys rule from tabulated fits
+#define ERI_RYS 2              /* Rys quadrature (Sec. II-C, eqs. 5-8) in FP64, every class:
+                                  nodes and weights of the Rys rule from tabulated fits
                                   (relative error 2e-16), 2D integrals by the Rys recurrences,
-                                  transfer to B and D per axis.  Classes with La+Lb+Lc+Ld <= 4
-                                  only (plan creation returns ERI_EUNSUPPORTED for others and
-                                  for ERI_PLAN_ALL_QUARTETS plans) */
+                                  transfer to B and D per axis, sum over nodes of Ix Iy Iz; one
+                                  lane per quartet for La+Lb+Lc+Ld <= 4, one workgroup per
+                                  quartet above.  Explicit quartet lists only (plan creation
+                                  returns ERI_EUNSUPPORTED for ERI_PLAN_ALL_QUARTETS) */
 
 typedef struct eri_plan eri_plan;
 

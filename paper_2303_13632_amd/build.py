@@ -91,7 +91,7 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed", "rys"), classes=
         rdeps = kdeps + [os.path.join(CSRC, "eri_rys.h"), os.path.join(GEN, "rys_table.h")]
         for s in srcs:
             obj = os.path.join(OBJ, os.path.basename(s) + ".o")
-            deps = hdeps if s in host else (rdeps if os.path.basename(s) == "eri_rys.hip" else kdeps)
+            deps = hdeps if s in host else (rdeps if os.path.basename(s).startswith("eri_rys") else kdeps)
             futs[ex.submit(_compile, s, obj, deps)] = s
         for fu in cf.as_completed(futs):
             obj, dt, did = fu.result()

@@ -441,7 +441,8 @@ def emit_mode_T(cp, prec, name):
     return name, em.text()
 
 
-RYS_LMAX = 4      # classes with L_tot <= 4 get a Rys-quadrature kernel (at most 3 roots)
+RYS_LMAX = 4      # classes with L_tot <= 4: one lane per quartet (at most 3 roots); larger: a workgroup
+RYS_DEG = 8       # degree of the Chebyshev series of the Rys rule (gen_rys_table.DEG)
 
 
 def emit_mode_R(cp, name):
@@ -463,7 +464,7 @@ def emit_mode_R(cp, name):
     Lab, Lcd = a + b, c + d
     N = cp.Ltot // 2 + 1
     em = Emitter()
-    flops = [30 + 2 * N * 3 * 14 + 4 * N]      # setup, the node/weight series, their scaling
+    flops = [30 + 2 * N * 3 * RYS_DEG + 4 * N]      # setup, the node/weight series, their scaling
 
     def count(expr):
         flops[0] += expr.count("*") + expr.count(" + ") + expr.count(" - ")
@@ -565,6 +566,249 @@ def emit_mode_R(cp, name):
     em.end()
     em.end()
     emit_store_T(em, cp, [(nm, ix) for nm, ix, _ in outs], "rys")
+    em.end()
+    return name, em.text(), flops[0]
+
+
+RYSW_LDS = 44 * 1024   # LDS of the 1D-integral buffer of one workgroup-per-quartet Rys kernel
+# launch variants of those kernels: (name suffix, LDS budget of the buffer, waves per SIMD)
+RYSW_VARIANTS = (("", RYSW_LDS, 1), ("_b", 100 * 1024, 1), ("_o2", RYSW_LDS, 2))
+
+
+def rysw_shape(cp, lds_budget=RYSW_LDS):
+    """(threads, ERIs per thread, primitive quartets per batch, 1D values
+    per node and axis) of the workgroup-per-quartet Rys kernel of a class."""
+    n = cp.n_eriq
+    NT = 256 if n > 1024 else 128 if n > 256 else 64
+    N = cp.Ltot // 2 + 1
+    NI = (cp.a + 1) * (cp.b + 1) * (cp.c + 1) * (cp.d + 1)
+    NB = max(1, min(NT // (3 * N), lds_budget // (3 * N * NI * 8)))
+    return NT, (n + NT - 1) // NT, NB, NI
+
+
+def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
+    """Rys-quadrature kernel of a class whose ERIs do not fit one lane (Sec.
+    II-C, eqs. 5-8): one workgroup per quartet, in the orientation cp.perm.
+    Per batch of NB primitive quartets:
+      1. one lane per primitive quartet and entry of the n-point Rys rule
+         at T (eri_rys_rule_entry: one node or weight), plus the
+         Gaussian-product setup, into LDS;
+      2. one lane per (primitive quartet, node, axis): the 2D integrals
+         G(n, m) of the Rys recurrences
+             G(n+1, 0) = C00 G(n, 0) + n B10 G(n-1, 0)
+             G(n, m+1) = C00' G(n, m) + m B01 G(n, m-1) + n B00 G(n-1, m),
+         then the transfers to B (I(a, b+1) = I(a+1, b) + (A-B) I(a, b)) and
+         to D, giving every 1D factor I(a', b', c', d') of that node and
+         axis, into LDS (the weight and prefactor ride on the z factors);
+      3. each thread owns ERIs k = thread + NT s of the computed layout and
+         adds sum over nodes of Ix Iy Iz, the three factors read from LDS at
+         offsets packed per ERI in a table.
+    Then b_max over the workgroup, and the store / quantise / pack of the
+    other kernels.  Returns (name, source, FLOPs per primitive quartet)."""
+    a, b, c, d = cp.a, cp.b, cp.c, cp.d
+    n = cp.n_eriq
+    NT, S, NB, NI = rysw_shape(cp, lds_budget)
+    N = cp.Ltot // 2 + 1
+    NQ = 2 * N + 17
+    nbuf = NB * N * 3 * NI
+    nbuf = max(nbuf, (4 * n + 7) // 8)            # the packed path stages int32 codes over it
+    dims = (a + 1, b + 1, c + 1, d + 1)
+
+    def idx1(t):
+        return ((t[0] * dims[1] + t[1]) * dims[2] + t[2]) * dims[3] + t[3]
+    ca, cb, cc, cd = comps(a), comps(b), comps(c), comps(d)
+    tab = []
+    for ai in ca:
+        for bi in cb:
+            for ci in cc:
+                for di in cd:
+                    ox, oy, oz = [idx1((ai[x], bi[x], ci[x], di[x])) + x * NI for x in range(3)]
+                    tab.append(ox | (oy << 10) | (oz << 20))
+    assert 3 * NI <= 1024 and len(tab) == n
+    em = Emitter()
+    flops = [30 + 2 * N * 3 * RYS_DEG + 2 * N]    # setup, the node/weight series, the weights' prefactor
+
+    def count(expr):
+        # one (node, axis) task: every node and axis of a primitive quartet runs it
+        flops[0] += 3 * N * (expr.count("*") + expr.count(" + ") + expr.count(" - "))
+    em("// class [%d%d|%d%d] computed as shells %s = [%d%d|%d%d], Rys quadrature (%d nodes), one workgroup of %d "
+       "threads per quartet" % (cp.user + (cp.perm, a, b, c, d, N, NT)))
+    em("static __device__ const uint32_t %s_tab[%d] = {" % (name, n))
+    for i in range(0, n, 12):
+        em("    " + ", ".join(str(v) for v in tab[i:i + 12]) + ",")
+    em("};")
+    if occupancy > 1:
+        em("__global__ __launch_bounds__(%d, %d) void %s(eri_class_args A)" % (NT, occupancy, name))
+    else:
+        em("__global__ __launch_bounds__(%d) void %s(eri_class_args A)" % (NT, name))
+    em.block("")
+    em("__shared__ double s_I[%d];   // [batch][node][axis][1D index]" % nbuf)
+    em("__shared__ double s_q[%d];   // per primitive quartet: nodes, weights, C00/C00' parts, B parts" % (NB * NQ))
+    em("__shared__ double s_red[%d];" % (NT // 64))
+    em("const int tid = threadIdx.x;")
+    em("const int64_t qi = blockIdx.x;")
+    em("if (qi >= A.n_items) return;   // uniform over the workgroup")
+    em("const eri_item it = A.items[qi];")
+    em("const bool sb = it.bra < 0, sk = it.ket < 0;   // pair stored in swapped order")
+    em("const eri_shell_pair BP = A.pairs[it.bra & 0x7fffffff];")
+    em("const eri_shell_pair KP = A.pairs[it.ket & 0x7fffffff];")
+    em("const int nket = KP.nprim;")
+    em("const int npq = BP.nprim * nket;")
+    em("uint32_t off[%d];" % S)
+    em("double acc[%d];" % S)
+    em("#pragma unroll")
+    em.block("for (int s = 0; s < %d; ++s)" % S)
+    em("const int k = tid + %d * s;" % NT)
+    em("off[s] = k < %d ? %s_tab[k] : 0u;" % (n, name))
+    em("acc[s] = 0.0;")
+    em.end()
+    em.block("for (int j0 = 0; j0 < npq; j0 += %d)" % NB)
+    em("__syncthreads();   // the previous batch's factors are consumed")
+    em("const int nb = min(%d, npq - j0);" % NB)
+    em.block("for (int t = tid; t < nb * %d; t += %d)" % (2 * N, NT))
+    em("const int jb = t / %d, e = t - jb * %d;" % (2 * N, 2 * N))
+    em("const int j = j0 + jb;")
+    em("const int ib = j / nket, ik = j - ib * nket;")
+    em("const eri_prim_pair B = A.prims[BP.prim_off + ib];")
+    em("const eri_prim_pair K = A.prims[KP.prim_off + ik];")
+    em("eri_pq_fp64 S;")
+    em("eri_pq_setup(B, K, S);")
+    em("const double v = eri_rys_rule_entry<%d>(S.T, e);" % N)
+    em("double* q = s_q + jb * %d;" % NQ)
+    em("q[e] = e < %d ? v : v * S.pref;" % N)
+    em.block("if (e == 0)")
+    for i in range(3):
+        em("q[%d] = B.PA[%d]; q[%d] = S.WP[%d]; q[%d] = K.PA[%d]; q[%d] = S.WQ[%d];"
+           % (2 * N + i, i, 2 * N + 3 + i, i, 2 * N + 6 + i, i, 2 * N + 9 + i, i))
+    em("q[%d] = S.hpq; q[%d] = B.hp; q[%d] = S.rho_p; q[%d] = K.hp; q[%d] = S.rho_q;"
+       % tuple(2 * N + 12 + i for i in range(5)))
+    em.end()
+    em.end()
+    em("__syncthreads();")
+    em.block("for (int t = tid; t < nb * %d; t += %d)" % (3 * N, NT))
+    em("const int jb = t / %d, rr = t - jb * %d;" % (3 * N, 3 * N))
+    em("const int r = rr / 3, ax = rr - 3 * r;")
+    em("const double* q = s_q + jb * %d;" % NQ)
+    em("const double u = q[r];")
+    em("const double B00 = u * q[%d];" % (2 * N + 12))
+    em("const double B10 = q[%d] - q[%d] * q[%d] * u;" % (2 * N + 13, 2 * N + 13, 2 * N + 14))
+    em("const double B01 = q[%d] - q[%d] * q[%d] * u;" % (2 * N + 15, 2 * N + 15, 2 * N + 16))
+    em("const double C00 = q[%d + ax] + u * q[%d + ax];" % (2 * N, 2 * N + 3))
+    em("const double D00 = q[%d + ax] + u * q[%d + ax];" % (2 * N + 6, 2 * N + 9))
+    em("const double AB = ax == 0 ? BP.AB[0] : ax == 1 ? BP.AB[1] : BP.AB[2];")
+    em("const double CD = ax == 0 ? KP.AB[0] : ax == 1 ? KP.AB[1] : KP.AB[2];")
+    em("const double g_0_0 = ax == 2 ? q[%d + r] : 1.0;" % N)
+    flops[0] += N * (5 + 3 * 4)
+    defined = {"g_0_0"}
+
+    def g(nn, m):
+        nm = "g_%d_%d" % (nn, m)
+        if nm in defined:
+            return nm
+        if m == 0:
+            expr = "C00 * %s" % g(nn - 1, 0)
+            if nn - 1 >= 1:
+                expr += " + %s * B10 * %s" % (lit(nn - 1), g(nn - 2, 0))
+        else:
+            expr = "D00 * %s" % g(nn, m - 1)
+            if m - 1 >= 1:
+                expr += " + %s * B01 * %s" % (lit(m - 1), g(nn, m - 2))
+            if nn >= 1:
+                expr += " + %s * B00 * %s" % (lit(nn), g(nn - 1, m - 1))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+
+    def kh(nn, cx, dx):
+        if dx == 0:
+            return g(nn, cx)
+        nm = "k_%d_%d_%d" % (nn, cx, dx)
+        if nm in defined:
+            return nm
+        expr = "%s + CD * %s" % (kh(nn, cx + 1, dx - 1), kh(nn, cx, dx - 1))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+
+    def ih(ax_a, bx, cx, dx):
+        if bx == 0:
+            return kh(ax_a, cx, dx)
+        nm = "i_%d_%d_%d_%d" % (ax_a, bx, cx, dx)
+        if nm in defined:
+            return nm
+        expr = "%s + AB * %s" % (ih(ax_a + 1, bx - 1, cx, dx), ih(ax_a, bx - 1, cx, dx))
+        em("const double %s = %s;" % (nm, expr))
+        count(expr)
+        defined.add(nm)
+        return nm
+    em("double* I = s_I + ((jb * %d + r) * 3 + ax) * %d;" % (N, NI))
+    for t in itertools.product(*[range(v) for v in dims]):
+        em("I[%d] = %s;" % (idx1(t), ih(*t)))
+    em.end()
+    em("__syncthreads();")
+    em.block("for (int jb = 0; jb < nb; ++jb)")
+    em("#pragma unroll")
+    em.block("for (int r = 0; r < %d; ++r)" % N)
+    em("const double* I = s_I + (jb * %d + r) * %d;" % (N, 3 * NI))
+    em("#pragma unroll")
+    em("for (int s = 0; s < %d; ++s) acc[s] = fma(I[off[s] & 1023u] * I[(off[s] >> 10) & 1023u], "
+       "I[off[s] >> 20], acc[s]);" % S)
+    em.end()
+    em.end()
+    em.end()
+    flops[0] += 3 * N * n
+    # epilogue: user-layout index of each owned ERI, b_max over the workgroup, stores
+    emit_slot(em, "qi")
+    em("const int64_t obase = oslot * %d;" % n)
+    nc = [ncart(L) for L in (a, b, c, d)]
+    em("int uix[%d];" % S)
+    em("double bmax = 0.0;")
+    em("#pragma unroll")
+    em.block("for (int s = 0; s < %d; ++s)" % S)
+    em("const int k = tid + %d * s;" % NT)
+    em("const int id_ = k %% %d, ic = (k / %d) %% %d, ib = (k / %d) %% %d, ia = k / %d;"
+       % (nc[3], nc[3], nc[2], nc[3] * nc[2], nc[1], nc[3] * nc[2] * nc[1]))
+    st = user_strides(cp)
+    bra = "ia * %d + ib * %d" % (st[0], st[1])
+    if a == b and st[0] != st[1]:
+        bra = "(sb ? ia * %d + ib * %d : %s)" % (st[1], st[0], bra)
+    ket = "ic * %d + id_ * %d" % (st[2], st[3])
+    if c == d and st[2] != st[3]:
+        ket = "(sk ? ic * %d + id_ * %d : %s)" % (st[3], st[2], ket)
+    em("uix[s] = %s + %s;" % (bra, ket))
+    em("if (k < %d) bmax = fmax(bmax, fabs(acc[s]));" % n)
+    em.end()
+    em.block("if (A.out_eri)")
+    em("#pragma unroll")
+    em("for (int s = 0; s < %d; ++s) if (tid + %d * s < %d) A.out_eri[obase + uix[s]] = acc[s];" % (S, NT, n))
+    em.end()
+    em.block("if (A.out_codes)")
+    em("for (int o = 32; o > 0; o >>= 1) bmax = fmax(bmax, __shfl_xor(bmax, o));")
+    em("if ((tid & 63) == 0) s_red[tid >> 6] = bmax;")
+    em("__syncthreads();")
+    em("bmax = s_red[0];")
+    em("#pragma unroll")
+    em("for (int w = 1; w < %d; ++w) bmax = fmax(bmax, s_red[w]);" % (NT // 64))
+    em("const double eps = bmax * A.cn;")
+    em("const double inv = eri_inverse_scale(eps);")
+    em("if (tid == 0 && A.out_scales) A.out_scales[oslot] = eps;")
+    em.block("if (A.pack_bits)")
+    em("const int wide = A.pack_bits > 16;")
+    em("#pragma unroll")
+    em("for (int s = 0; s < %d; ++s) if (tid + %d * s < %d) eri_stage_code(s_I, uix[s], wide, "
+       "eri_quantize(acc[s], eps, inv, A.qmax));" % (S, NT, n))
+    em("__syncthreads();")
+    em("eri_pack_group(s_I, %d, 1, A.pack_bits, A.pack_per, (int)A.pack_wpq, "
+       "reinterpret_cast<uint32_t*>(A.out_codes), gq, A.ring, tid, %d);" % (n, NT))
+    em.end()
+    em.block("else")
+    em("#pragma unroll")
+    em("for (int s = 0; s < %d; ++s) if (tid + %d * s < %d) eri_store_code(A.out_codes, obase + uix[s], "
+       "A.code_bytes, eri_quantize(acc[s], eps, inv, A.qmax));" % (S, NT, n))
+    em.end()
+    em.end()
     em.end()
     return name, em.text(), flops[0]
 
@@ -1783,6 +2027,37 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
         write_if_changed(fn, "\n".join(parts))
         files.append(fn)
         regs.append(("rys", "eri_register_rys"))
+        # the larger classes: one workgroup per quartet, grouped by L_tot into
+        # translation units of at most 24 classes
+        big = sorted((u for u in classes if sum(u) > RYS_LMAX), key=lambda u: (sum(u), class_id(*u)))
+        for gi in range(0, len(big), 24):
+            parts = [HEADER, '#include "eri_rys.h"', '#include "eri_dispatch.h"']
+            lines_ = []
+            for user in big[gi:gi + 24]:
+                cp = plans.get(user) or ClassPlan(*user, **overrides.get(user, {}))
+                plans[user] = cp
+                pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
+                c5 = class_id5(*user)
+                k = 0
+                for (suffix, budget, occ), tag in zip(RYSW_VARIANTS, (TAG_DEFAULT, TAG_ALT, TAG_OCC2)):
+                    if k and rysw_shape(cp, budget) == rysw_shape(cp) and occ == 1:
+                        continue   # the larger budget changes nothing for this class
+                    name = kernel_name("rys", cp.user) + suffix
+                    _, src, fpq = emit_mode_RW(cp, name, budget, occ)
+                    parts.append(src)
+                    NT = rysw_shape(cp, budget)[0]
+                    info = "{(const void*)%s, 1, %d, 1, %d, %d, %d, %d, %d, 0, 0}" % (
+                        name, NT, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, tag)
+                    if k == 0:
+                        lines_.append("    t[%d] = %s;" % (c5, info))
+                    lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
+                    k += 1
+            fname = "eri_register_rysw_g%02d" % (gi // 24)
+            parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
+            fn = os.path.join(outdir, "eri_rysw_g%02d.hip" % (gi // 24))
+            write_if_changed(fn, "\n".join(parts))
+            files.append(fn)
+            regs.append(("rys", fname))
     lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
     for prec, fname in regs:
         lines.append("void %s(eri_kernel_info* t, eri_kernel_info* v);" % fname)

@@ -1127,7 +1127,7 @@ extern "C" int eri_plan_set_variants(eri_plan* p, const int32_t* v)
     if (!p || !v) return ERI_EINVAL;
     const eri_kernel_info* var = eri_kernel_variants(table_index(p->precision));
     // a class without quartets in the plan may keep variant 0 even where its
-    // precision has no kernel (the Rys family covers L_tot <= 4 only)
+    // precision has no kernel
     for (int c = 0; c < 256; ++c) {
         if (v[c] < 0 || v[c] >= ERI_MAXVAR) return ERI_EINVAL;
         if (!var[class_id5_of(c) * ERI_MAXVAR + v[c]].fn && (v[c] != 0 || p->class_count[c])) return ERI_EINVAL;

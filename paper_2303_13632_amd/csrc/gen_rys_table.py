@@ -2,9 +2,10 @@
 rules for the measure exp(-T x) x^(-1/2) / 2 dx on x in [0, 1] (x = t^2),
 whose moments are the Boys values F_k(T).  For n = 1 .. NMAX the nodes x_i(T)
 and weights w_i(T) are stored as Chebyshev series on intervals of T of width
-H below TMAX; above TMAX the measure is the half-line one up to a relative
-error below 1e-17, so x_i = s_i / T and w_i = W_i / (2 sqrt(T)) with (s_i, W_i)
-the Gauss rule of s^(-1/2) exp(-s) on [0, inf).
+H below TMAX; above TMAX the rule of the half-line measure agrees with the
+finite one to about 2e-16 relative for every n <= NMAX (at T = 64 the 7-point
+rules still differ by 4e-12), so x_i = s_i / T and w_i = W_i / (2 sqrt(T))
+with (s_i, W_i) the Gauss rule of s^(-1/2) exp(-s) on [0, inf).
 
 The reference values are computed here in 40-digit arithmetic (mpmath):
 ordinary moments from the incomplete gamma function, recurrence coefficients
@@ -15,9 +16,9 @@ import math
 import os
 import sys
 
-NMAX = 4          # points: classes up to L_tot = 6
+NMAX = 7          # points: classes up to L_tot = 12
 H = 0.25          # interval width in T
-TMAX = 64.0       # first T of the half-line rule
+TMAX = 80.0       # first T of the half-line rule
 DEG = 8           # Chebyshev degree per interval
 
 
@@ -95,44 +96,51 @@ def _cheb_eval(c, x):
     return x * b1 - b2 + c[0]
 
 
-def tables(check=True):
-    """(coefficient array, max relative error of the check, half-line rules)."""
+def _fit_n(n, check=True):
+    """Coefficients of the n-point rule on every interval (flattened
+    [interval][2n functions][DEG + 1]) and the largest relative error of the
+    fits against fresh reference values between the interpolation nodes."""
     mp = _mp()
     nint = int(round(TMAX / H))
-    coef = []          # [n][interval][2n functions][DEG + 1], flattened in that order
+    coef = []
     worst = 0.0
-    for n in range(1, NMAX + 1):
-        for j in range(nint):
-            a, b = mp.mpf(j) * H, mp.mpf(j + 1) * H
+    for j in range(nint):
+        a, b = mp.mpf(j) * H, mp.mpf(j + 1) * H
 
-            def f(T, n=n):
-                x, w = rule(mp, n, T)
-                return x + w
-            c = _cheb_fit(mp, f, a, b, DEG)
-            cf = [[float(v) for v in cq] for cq in c]
-            coef.extend(v for cq in cf for v in cq)
-            if check:
-                for t in (0.137, 0.5, 0.863):
-                    T = a + (b - a) * t
-                    ref = f(T)
-                    xloc = float(2 * t - 1)
-                    for q, cq in enumerate(cf):
-                        got = _cheb_eval(cq, xloc)
-                        worst = max(worst, abs(got - float(ref[q])) / abs(float(ref[q])))
-    half = []
-    for n in range(1, NMAX + 1):
-        s, W = half_line_rule(mp, n)
-        half.append(([float(v) for v in s], [float(v) for v in W]))
+        def f(T):
+            x, w = rule(mp, n, T)
+            return x + w
+        c = _cheb_fit(mp, f, a, b, DEG)
+        cf = [[float(v) for v in cq] for cq in c]
+        coef.extend(v for cq in cf for v in cq)
+        if check:
+            for t in (0.137, 0.5, 0.863):
+                T = a + (b - a) * t
+                ref = f(T)
+                xloc = float(2 * t - 1)
+                for q, cq in enumerate(cf):
+                    got = _cheb_eval(cq, xloc)
+                    worst = max(worst, abs(got - float(ref[q])) / abs(float(ref[q])))
+    s, W = half_line_rule(mp, n)
+    half = ([float(v) for v in s], [float(v) for v in W])
     if check:
         # the half-line rule against the finite one at TMAX and beyond
-        for n in range(1, NMAX + 1):
-            for T in (TMAX, TMAX + 7.3, 2 * TMAX):
-                x, w = rule(mp, n, T)
-                s, W = half[n - 1]
-                for i in range(n):
-                    worst = max(worst, abs(s[i] / T - float(x[i])) / float(x[i]),
-                                abs(W[i] / (2 * math.sqrt(T)) - float(w[i])) / float(w[i]))
+        for T in (TMAX, TMAX + 7.3, 2 * TMAX):
+            x, w = rule(mp, n, T)
+            for i in range(n):
+                worst = max(worst, abs(half[0][i] / T - float(x[i])) / float(x[i]),
+                            abs(half[1][i] / (2 * math.sqrt(T)) - float(w[i])) / float(w[i]))
     return coef, worst, half
+
+
+def tables(check=True, jobs=None):
+    """(coefficient arrays per n, max relative error of the checks,
+    half-line rules per n); one process per rule size."""
+    import concurrent.futures as cf
+    jobs = jobs or min(NMAX, os.cpu_count() or 1)
+    with cf.ProcessPoolExecutor(max_workers=jobs) as ex:
+        res = list(ex.map(_fit_n, range(1, NMAX + 1), [check] * NMAX))
+    return [r[0] for r in res], max(r[1] for r in res), [r[2] for r in res]
 
 
 def write(path):
@@ -149,16 +157,13 @@ def write(path):
              "#define ERI_RYS_DEG %d" % DEG,
              "#define ERI_RYS_H %.17g" % H,
              "#define ERI_RYS_TMAX %.17g" % TMAX]
-    # offsets of n's block: sum over m < n of nint * 2m * (DEG + 1)
-    offs, o = [], 0
+    # one array per rule size, so a translation unit keeps only those it uses
     for n in range(1, NMAX + 1):
-        offs.append(o)
-        o += nint * 2 * n * (DEG + 1)
-    lines.append("static __constant__ int eri_rys_off[%d] = {%s};" % (NMAX, ", ".join(str(v) for v in offs)))
-    lines.append("static __device__ const double eri_rys_coef[%d] = {" % len(coef))
-    for i in range(0, len(coef), 4):
-        lines.append("    " + ", ".join("%.17g" % v for v in coef[i:i + 4]) + ",")
-    lines.append("};")
+        c = coef[n - 1]
+        lines.append("static __device__ const double eri_rys_coef%d[%d] = {" % (n, len(c)))
+        for i in range(0, len(c), 4):
+            lines.append("    " + ", ".join("%.17g" % v for v in c[i:i + 4]) + ",")
+        lines.append("};")
     hs = [v for n in range(NMAX) for v in half[n][0]]
     hw = [v for n in range(NMAX) for v in half[n][1]]
     lines.append("static __constant__ double eri_rys_half_s[%d] = {%s};" % (len(hs), ", ".join("%.17g" % v for v in hs)))

@@ -1,9 +1,10 @@
 """GPU parity of the Rys-quadrature kernels (precision "rys": Sec. II-C,
-eqs. 5-8, for the classes with La+Lb+Lc+Ld <= 4) against the oracle: FP64
-ERIs within 1e-12 Ha (quartets that miss it against the double oracle are
-refereed by its __float128 build), fused codes and scales bit-identical to the
-oracle's compressor fed the GPU's doubles, every launch variant; and the
-classes and plan kinds the family does not cover are refused."""
+eqs. 5-8, every class: one lane per quartet for La+Lb+Lc+Ld <= 4, one
+workgroup per quartet above) against the oracle: FP64 ERIs within 1e-12 Ha
+(quartets that miss it against the double oracle are refereed by its
+__float128 build), fused codes and scales bit-identical to the oracle's
+compressor fed the GPU's doubles, every launch variant; and the plan kinds
+the family does not cover are refused."""
 import os
 
 import numpy as np
@@ -16,8 +17,9 @@ from parity_util import check_quartets
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 THREADS = min(16, os.cpu_count() or 1)
-N_PER_CLASS = 67
-RYS_CLASSES = [c for c in range(256) if sum(W.class_of(c)) <= 4]
+N_PER_CLASS = 41
+RYS_CLASSES = list(range(256))
+LANE_CLASSES = [c for c in range(256) if sum(W.class_of(c)) <= 4]
 
 
 def _blocks(sizes):
@@ -28,7 +30,7 @@ def _blocks(sizes):
 
 def test_rys_classes_vs_oracle():
     from paper_2303_13632_amd import eri
-    assert len(RYS_CLASSES) == 66
+    assert len(LANE_CLASSES) == 66
     parts = [W.class_case(cid, n_quartets=N_PER_CLASS, seed=W.SEED_BASE + 95) for cid in RYS_CLASSES]
     shells, quartets = W.merge(parts)
     ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
@@ -50,15 +52,11 @@ def test_rys_classes_vs_oracle():
         assert np.array_equal(oe, s.cpu().numpy()[: plan.n_quartets]), k
         assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32)), k
         del e, c, s
-    assert plan.kernel_name(RYS_CLASSES[-1]).startswith("eri_rys_c")
+    assert all(plan.kernel_name(c).startswith("eri_rys_c") for c in RYS_CLASSES)
 
 
 def test_rys_refusals():
     from paper_2303_13632_amd import eri
-    # a class above L_tot = 4 has no Rys kernel
-    sh, q = W.class_case(W.class_id(2, 1, 1, 1), n_quartets=4)
-    with pytest.raises(eri.EriError):
-        eri.Plan(sh, q, precision="rys", bits=16)
     # screened (all-quartet) plans are not offered in this precision
     sh = W.molecule_basis(n_heavy=1, n_h=1, lattice=(2, 1, 1))
     with pytest.raises(eri.EriError):
@@ -87,3 +85,31 @@ def test_rys_codes(bits, packed):
         assert np.array_equal(c.cpu().numpy().view(np.uint8)[: len(ref)], ref)
     else:
         assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32))
+
+
+def test_rys_degenerate_geometries():
+    """One centre (T = 0, the odd-parity zeros), far-apart pairs (T beyond
+    the tabulated range: the half-line rule), tight exponents and K = 3 on
+    every shell (81 primitive quartets: several batches of the workgroup
+    kernels, the last one ragged), for lane and workgroup classes."""
+    from paper_2303_13632_amd import eri
+    parts = []
+    for cid in (85, 27, 150, 228, 170, 255, 238, 187):
+        sh, q = W.random_class_quartets(*W.class_of(cid), n_quartets=12, seed=4242 + cid,
+                                        k_fixed=3 if cid % 2 else None)
+        sh["xyz"] = sh["xyz"].copy()
+        sh["exps"] = sh["exps"].copy()
+        sh["xyz"][0:16] = sh["xyz"][0]                              # quartets 0..3: one centre
+        sh["xyz"][16:24] = sh["xyz"][16] + np.array([0, 0, 40.0])   # quartets 4, 5: far apart
+        sh["exps"][: len(sh["exps"]) // 3] *= 50.0                   # tight
+        parts.append((sh, q))
+    shells, quartets = W.merge(parts)
+    ref, ref_off, sizes = O.eri(shells, quartets, n_threads=THREADS)
+    plan = eri.Plan(shells, quartets, precision="rys", bits=16)
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    vals = e.cpu().numpy()[: plan.n_eri]
+    got = plan.to_user(vals)
+    err, nref = check_quartets(shells, quartets, got, ref, ref_off, sizes, THREADS)
+    print("degenerate: max |err| %.3e (%d refereed)" % (err, nref), flush=True)
