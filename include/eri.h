@@ -69,6 +69,10 @@ extern "C" {
                                   lane per quartet for La+Lb+Lc+Ld <= 4, one workgroup per
                                   quartet above.  Explicit quartet lists only (plan creation
                                   returns ERI_EUNSUPPORTED for ERI_PLAN_ALL_QUARTETS) */
+#define ERI_RYS_FP32 3         /* the same Rys kernels with the paper's single-precision stages
+                                  (Sec. II-C): 2D recurrences, transfers, 1D factors and the
+                                  node sum in FP32; the rule, the setup, the weights' prefactor
+                                  and the contraction in FP64.  Same restrictions as ERI_RYS */
 
 typedef struct eri_plan eri_plan;
 
@@ -76,7 +80,7 @@ typedef struct eri_plan eri_plan;
 #define ERI_PLAN_PACKED 2        /* codes written as the packed 512-bit word stream (see eri_compute) */
 
 typedef struct {
-    int32_t precision;          /* ERI_FP64, ERI_FP32_MIXED or ERI_RYS */
+    int32_t precision;          /* ERI_FP64, ERI_FP32_MIXED, ERI_RYS or ERI_RYS_FP32 */
     int32_t bits;               /* code width n of eq. 10: 0 = no codes, else 2..32 */
     int32_t device;             /* HIP device ordinal */
     int32_t flags;              /* ERI_PLAN_ALL_QUARTETS and/or ERI_PLAN_PACKED, or 0 */

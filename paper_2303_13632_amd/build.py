@@ -54,7 +54,7 @@ def _compile(src, obj, deps):
     return obj, time.time() - t0, True
 
 
-def build(jobs=None, verbose=True, precisions=("fp64", "mixed", "rys"), classes=None):
+def build(jobs=None, verbose=True, precisions=("fp64", "mixed", "rys", "rys32"), classes=None):
     sys.path.insert(0, CSRC)
     import codegen  # noqa: E402
     import gen_boys_table  # noqa: E402
@@ -70,7 +70,7 @@ def build(jobs=None, verbose=True, precisions=("fp64", "mixed", "rys"), classes=
     rt = os.path.join(GEN, "rys_table.h")
     rstamp = rt + ".sha"
     rdig = _digest([os.path.join(CSRC, "gen_rys_table.py")])
-    if "rys" in precisions and not (os.path.exists(rt) and os.path.exists(rstamp) and open(rstamp).read() == rdig):
+    if ("rys" in precisions or "rys32" in precisions) and not (os.path.exists(rt) and os.path.exists(rstamp) and open(rstamp).read() == rdig):
         err = gen_rys_table.write(rt)
         with open(rstamp, "w") as f:
             f.write(rdig)

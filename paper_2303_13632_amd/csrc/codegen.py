@@ -33,7 +33,7 @@ import itertools
 import math
 import os
 
-REALS = {"fp64": "double", "mixed": "float", "rys": "double"}
+REALS = {"fp64": "double", "mixed": "float", "rys": "double", "rys32": "float"}
 
 # kernel name -> 1 if its packed-stream path stages codes in dynamic LDS (sized
 # at launch), 0 if in the kernel's own LDS once the HRR staging is consumed
@@ -445,9 +445,14 @@ RYS_LMAX = 4      # classes with L_tot <= 4: one lane per quartet (at most 3 roo
 RYS_DEG = 8       # degree of the Chebyshev series of the Rys rule (gen_rys_table.DEG)
 
 
-def emit_mode_R(cp, name):
+def emit_mode_R(cp, name, real="double"):
     """Rys-quadrature kernel of a class (Sec. II-C, eqs. 5-8), one lane per
-    quartet, FP64, in the orientation cp.perm of the Obara-Saika kernels.
+    quartet, in the orientation cp.perm of the Obara-Saika kernels.  With
+    real = "float" the recurrences, transfers and the node sum run in FP32
+    (the paper's single-precision Rys stages): the rule, the setup and the
+    prefactor stay FP64, G(0, 0) of z carries the weight only, and each
+    primitive quartet's FP32 node sum is scaled by the FP64 prefactor into the
+    FP64 contraction sums.
     Per primitive quartet the n = L_tot/2 + 1 nodes x_r = t_r^2 and weights
     w_r of the Rys rule at T come from the tabulated fits (eri_rys_rule);
     per node and axis the 2D integrals G(n, m), n <= L_a + L_b, m <= L_c + L_d,
@@ -495,12 +500,19 @@ def emit_mode_R(cp, name):
     em("eri_pq_setup(B, K, S);")
     em("double rx[%d], rw[%d];" % (N, N))
     em("eri_rys_rule<%d>(S.T, rx, rw);" % N)
+    f32 = real == "float"
+
+    def rl(x):
+        return lit(x) + ("f" if f32 else "")
+    if f32:
+        for nm, _, _ in outs:
+            em("float t%s = 0.0f;" % nm)
     em("#pragma unroll")
     em.block("for (int r = 0; r < %d; ++r)" % N)
     em("const double u = rx[r];")
-    em("const double B00 = u * S.hpq;")
-    em("const double B10 = B.hp - B.hp * S.rho_p * u;")
-    em("const double B01 = K.hp - K.hp * S.rho_q * u;")
+    em("const %s B00 = (%s)(u * S.hpq);" % (real, real))
+    em("const %s B10 = (%s)(B.hp - B.hp * S.rho_p * u);" % (real, real))
+    em("const %s B01 = (%s)(K.hp - K.hp * S.rho_q * u);" % (real, real))
     flops[0] += 5
     defined = set()
 
@@ -510,18 +522,21 @@ def emit_mode_R(cp, name):
             return nm
         i = "xyz".index(ax)
         if n == 0 and m == 0:
-            expr = "rw[r] * S.pref" if ax == "z" else "1.0"
+            if f32:
+                expr = "(float)rw[r]" if ax == "z" else "1.0f"
+            else:
+                expr = "rw[r] * S.pref" if ax == "z" else "1.0"
         elif m == 0:
             expr = "C0%s * %s" % (ax, g(ax, n - 1, 0))
             if n - 1 >= 1:
-                expr += " + %s * B10 * %s" % (lit(n - 1), g(ax, n - 2, 0))
+                expr += " + %s * B10 * %s" % (rl(n - 1), g(ax, n - 2, 0))
         else:
             expr = "D0%s * %s" % (ax, g(ax, n, m - 1))
             if m - 1 >= 1:
-                expr += " + %s * B01 * %s" % (lit(m - 1), g(ax, n, m - 2))
+                expr += " + %s * B01 * %s" % (rl(m - 1), g(ax, n, m - 2))
             if n >= 1:
-                expr += " + %s * B00 * %s" % (lit(n), g(ax, n - 1, m - 1))
-        em("const double %s = %s;" % (nm, expr))
+                expr += " + %s * B00 * %s" % (rl(n), g(ax, n - 1, m - 1))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
@@ -534,7 +549,7 @@ def emit_mode_R(cp, name):
         if nm in defined:
             return nm
         expr = "%s + CD%s * %s" % (kh(ax, n, cx + 1, dx - 1), ax, kh(ax, n, cx, dx - 1))
-        em("const double %s = %s;" % (nm, expr))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
@@ -547,22 +562,26 @@ def emit_mode_R(cp, name):
         if nm in defined:
             return nm
         expr = "%s + AB%s * %s" % (ih(ax, ax_a + 1, bx - 1, cx, dx), ax, ih(ax, ax_a, bx - 1, cx, dx))
-        em("const double %s = %s;" % (nm, expr))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
     for i, ax in enumerate("xyz"):
-        em("const double C0%s = B.PA[%d] + u * S.WP[%d];" % (ax, i, i))
-        em("const double D0%s = K.PA[%d] + u * S.WQ[%d];" % (ax, i, i))
-        em("const double AB%s = BP.AB[%d], CD%s = KP.AB[%d];" % (ax, i, ax, i))
+        em("const %s C0%s = (%s)(B.PA[%d] + u * S.WP[%d]);" % (real, ax, real, i, i))
+        em("const %s D0%s = (%s)(K.PA[%d] + u * S.WQ[%d]);" % (real, ax, real, i, i))
+        em("const %s AB%s = (%s)BP.AB[%d], CD%s = (%s)KP.AB[%d];" % (real, ax, real, i, ax, real, i))
         flops[0] += 4
     for nm, _, (ai, bi, ci, di) in outs:
         fx = ih("x", ai[0], bi[0], ci[0], di[0])
         fy = ih("y", ai[1], bi[1], ci[1], di[1])
         fz = ih("z", ai[2], bi[2], ci[2], di[2])
-        em("%s += %s * %s * %s;" % (nm, fx, fy, fz))
+        em("%s += %s * %s * %s;" % (("t" + nm) if f32 else nm, fx, fy, fz))
         flops[0] += 3
     em.end()
+    if f32:
+        for nm, _, _ in outs:
+            em("%s = fma((double)t%s, S.pref, %s);" % (nm, nm, nm))
+        flops[0] += 2 * len(outs)
     em.end()
     em.end()
     emit_store_T(em, cp, [(nm, ix) for nm, ix, _ in outs], "rys")
@@ -571,22 +590,27 @@ def emit_mode_R(cp, name):
 
 
 RYSW_LDS = 44 * 1024   # LDS of the 1D-integral buffer of one workgroup-per-quartet Rys kernel
-# launch variants of those kernels: (name suffix, LDS budget of the buffer, waves per SIMD)
-RYSW_VARIANTS = (("", RYSW_LDS, 1), ("_b", 100 * 1024, 1), ("_o2", RYSW_LDS, 2))
+# launch variants of those kernels:
+# (name suffix, LDS budget of the buffer, waves per SIMD, thread scale, node loop unrolled, tag)
+RYSW_VARIANTS = (("", RYSW_LDS, 1, 1, True, 0), ("_b", 100 * 1024, 1, 1, True, 7), ("_o2", RYSW_LDS, 2, 1, True, 2),
+                 ("_w", RYSW_LDS, 4, 2, True, 8), ("_wo2", RYSW_LDS, 2, 2, True, 9),
+                 ("_n", RYSW_LDS, 1, 1, False, 10), ("_no2", RYSW_LDS, 2, 1, False, 11),
+                 ("_nwo2", RYSW_LDS, 2, 2, False, 12))
 
 
-def rysw_shape(cp, lds_budget=RYSW_LDS):
+def rysw_shape(cp, lds_budget=RYSW_LDS, vbytes=8, nt_scale=1):
     """(threads, ERIs per thread, primitive quartets per batch, 1D values
-    per node and axis) of the workgroup-per-quartet Rys kernel of a class."""
+    per node and axis) of the workgroup-per-quartet Rys kernel of a class
+    (1D values of vbytes bytes)."""
     n = cp.n_eriq
-    NT = 256 if n > 1024 else 128 if n > 256 else 64
+    NT = nt_scale * (256 if n > 1024 else 128 if n > 256 else 64)
     N = cp.Ltot // 2 + 1
     NI = (cp.a + 1) * (cp.b + 1) * (cp.c + 1) * (cp.d + 1)
-    NB = max(1, min(NT // (3 * N), lds_budget // (3 * N * NI * 8)))
+    NB = max(1, min(NT // (3 * N), lds_budget // (3 * N * NI * vbytes)))
     return NT, (n + NT - 1) // NT, NB, NI
 
 
-def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
+def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1, real="double", nt_scale=1, unroll=True):
     """Rys-quadrature kernel of a class whose ERIs do not fit one lane (Sec.
     II-C, eqs. 5-8): one workgroup per quartet, in the orientation cp.perm.
     Per batch of NB primitive quartets:
@@ -604,14 +628,24 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
          adds sum over nodes of Ix Iy Iz, the three factors read from LDS at
          offsets packed per ERI in a table.
     Then b_max over the workgroup, and the store / quantise / pack of the
-    other kernels.  Returns (name, source, FLOPs per primitive quartet)."""
+    other kernels.  With real = "float" the recurrences, transfers, 1D
+    factors and the node sum are FP32 (the paper's single-precision Rys
+    stages); the rule, the setup and the prefactor stay FP64, the z factors
+    carry the weight only, and each primitive quartet's FP32 node sum is
+    scaled by the FP64 prefactor into FP64 contraction sums.  Returns (name,
+    source, FLOPs per primitive quartet)."""
     a, b, c, d = cp.a, cp.b, cp.c, cp.d
     n = cp.n_eriq
-    NT, S, NB, NI = rysw_shape(cp, lds_budget)
+    f32 = real == "float"
+    vb = 4 if f32 else 8
+    NT, S, NB, NI = rysw_shape(cp, lds_budget, vb, nt_scale)
     N = cp.Ltot // 2 + 1
-    NQ = 2 * N + 17
+    NQ = 2 * N + 18
     nbuf = NB * N * 3 * NI
-    nbuf = max(nbuf, (4 * n + 7) // 8)            # the packed path stages int32 codes over it
+    nbuf = max(nbuf, (4 * n + vb - 1) // vb)      # the packed path stages int32 codes over it
+
+    def rl(x):
+        return lit(x) + ("f" if f32 else "")
     dims = (a + 1, b + 1, c + 1, d + 1)
 
     def idx1(t):
@@ -642,7 +676,7 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
     else:
         em("__global__ __launch_bounds__(%d) void %s(eri_class_args A)" % (NT, name))
     em.block("")
-    em("__shared__ double s_I[%d];   // [batch][node][axis][1D index]" % nbuf)
+    em("__shared__ %s s_I[%d];   // [batch][node][axis][1D index]" % (real, nbuf))
     em("__shared__ double s_q[%d];   // per primitive quartet: nodes, weights, C00/C00' parts, B parts" % (NB * NQ))
     em("__shared__ double s_red[%d];" % (NT // 64))
     em("const int tid = threadIdx.x;")
@@ -675,8 +709,12 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
     em("eri_pq_setup(B, K, S);")
     em("const double v = eri_rys_rule_entry<%d>(S.T, e);" % N)
     em("double* q = s_q + jb * %d;" % NQ)
-    em("q[e] = e < %d ? v : v * S.pref;" % N)
+    if f32:
+        em("q[e] = v;")
+    else:
+        em("q[e] = e < %d ? v : v * S.pref;" % N)
     em.block("if (e == 0)")
+    em("q[%d] = S.pref;" % (2 * N + 17))
     for i in range(3):
         em("q[%d] = B.PA[%d]; q[%d] = S.WP[%d]; q[%d] = K.PA[%d]; q[%d] = S.WQ[%d];"
            % (2 * N + i, i, 2 * N + 3 + i, i, 2 * N + 6 + i, i, 2 * N + 9 + i, i))
@@ -690,14 +728,15 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
     em("const int r = rr / 3, ax = rr - 3 * r;")
     em("const double* q = s_q + jb * %d;" % NQ)
     em("const double u = q[r];")
-    em("const double B00 = u * q[%d];" % (2 * N + 12))
-    em("const double B10 = q[%d] - q[%d] * q[%d] * u;" % (2 * N + 13, 2 * N + 13, 2 * N + 14))
-    em("const double B01 = q[%d] - q[%d] * q[%d] * u;" % (2 * N + 15, 2 * N + 15, 2 * N + 16))
-    em("const double C00 = q[%d + ax] + u * q[%d + ax];" % (2 * N, 2 * N + 3))
-    em("const double D00 = q[%d + ax] + u * q[%d + ax];" % (2 * N + 6, 2 * N + 9))
-    em("const double AB = ax == 0 ? BP.AB[0] : ax == 1 ? BP.AB[1] : BP.AB[2];")
-    em("const double CD = ax == 0 ? KP.AB[0] : ax == 1 ? KP.AB[1] : KP.AB[2];")
-    em("const double g_0_0 = ax == 2 ? q[%d + r] : 1.0;" % N)
+    R = real
+    em("const %s B00 = (%s)(u * q[%d]);" % (R, R, 2 * N + 12))
+    em("const %s B10 = (%s)(q[%d] - q[%d] * q[%d] * u);" % (R, R, 2 * N + 13, 2 * N + 13, 2 * N + 14))
+    em("const %s B01 = (%s)(q[%d] - q[%d] * q[%d] * u);" % (R, R, 2 * N + 15, 2 * N + 15, 2 * N + 16))
+    em("const %s C00 = (%s)(q[%d + ax] + u * q[%d + ax]);" % (R, R, 2 * N, 2 * N + 3))
+    em("const %s D00 = (%s)(q[%d + ax] + u * q[%d + ax]);" % (R, R, 2 * N + 6, 2 * N + 9))
+    em("const %s AB = (%s)(ax == 0 ? BP.AB[0] : ax == 1 ? BP.AB[1] : BP.AB[2]);" % (R, R))
+    em("const %s CD = (%s)(ax == 0 ? KP.AB[0] : ax == 1 ? KP.AB[1] : KP.AB[2]);" % (R, R))
+    em("const %s g_0_0 = ax == 2 ? (%s)q[%d + r] : %s;" % (R, R, N, rl(1)))
     flops[0] += N * (5 + 3 * 4)
     defined = {"g_0_0"}
 
@@ -708,14 +747,14 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
         if m == 0:
             expr = "C00 * %s" % g(nn - 1, 0)
             if nn - 1 >= 1:
-                expr += " + %s * B10 * %s" % (lit(nn - 1), g(nn - 2, 0))
+                expr += " + %s * B10 * %s" % (rl(nn - 1), g(nn - 2, 0))
         else:
             expr = "D00 * %s" % g(nn, m - 1)
             if m - 1 >= 1:
-                expr += " + %s * B01 * %s" % (lit(m - 1), g(nn, m - 2))
+                expr += " + %s * B01 * %s" % (rl(m - 1), g(nn, m - 2))
             if nn >= 1:
-                expr += " + %s * B00 * %s" % (lit(nn), g(nn - 1, m - 1))
-        em("const double %s = %s;" % (nm, expr))
+                expr += " + %s * B00 * %s" % (rl(nn), g(nn - 1, m - 1))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
@@ -727,7 +766,7 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
         if nm in defined:
             return nm
         expr = "%s + CD * %s" % (kh(nn, cx + 1, dx - 1), kh(nn, cx, dx - 1))
-        em("const double %s = %s;" % (nm, expr))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
@@ -739,23 +778,40 @@ def emit_mode_RW(cp, name, lds_budget=RYSW_LDS, occupancy=1):
         if nm in defined:
             return nm
         expr = "%s + AB * %s" % (ih(ax_a + 1, bx - 1, cx, dx), ih(ax_a, bx - 1, cx, dx))
-        em("const double %s = %s;" % (nm, expr))
+        em("const %s %s = %s;" % (real, nm, expr))
         count(expr)
         defined.add(nm)
         return nm
-    em("double* I = s_I + ((jb * %d + r) * 3 + ax) * %d;" % (N, NI))
-    for t in itertools.product(*[range(v) for v in dims]):
-        em("I[%d] = %s;" % (idx1(t), ih(*t)))
+    em("%s* I = s_I + ((jb * %d + r) * 3 + ax) * %d;" % (real, N, NI))
+    # column by column of the ket (c', d'): its transfers to B, stored at once;
+    # in the variants for the largest classes (node loop not unrolled) a
+    # scheduling barrier between columns keeps the compiler from hoisting
+    # every column's work (those ran out of registers); elsewhere it cost time
+    for cdx in itertools.product(range(dims[2]), range(dims[3])):
+        for abx in itertools.product(range(dims[0]), range(dims[1])):
+            t = abx + cdx
+            em("I[%d] = %s;" % (idx1(t), ih(*t)))
+        if NI > 64 and not unroll:
+            em("__builtin_amdgcn_sched_barrier(0);")
     em.end()
     em("__syncthreads();")
     em.block("for (int jb = 0; jb < nb; ++jb)")
-    em("#pragma unroll")
+    if f32:
+        em("float t[%d];" % S)
+        em("#pragma unroll")
+        em("for (int s = 0; s < %d; ++s) t[s] = 0.0f;" % S)
+    em("#pragma unroll" if unroll else "#pragma unroll 1")
     em.block("for (int r = 0; r < %d; ++r)" % N)
-    em("const double* I = s_I + (jb * %d + r) * %d;" % (N, 3 * NI))
+    em("const %s* I = s_I + (jb * %d + r) * %d;" % (real, N, 3 * NI))
     em("#pragma unroll")
-    em("for (int s = 0; s < %d; ++s) acc[s] = fma(I[off[s] & 1023u] * I[(off[s] >> 10) & 1023u], "
-       "I[off[s] >> 20], acc[s]);" % S)
+    em("for (int s = 0; s < %d; ++s) %s = fma(I[off[s] & 1023u] * I[(off[s] >> 10) & 1023u], "
+       "I[off[s] >> 20], %s);" % ((S,) + (("t[s]", "t[s]") if f32 else ("acc[s]", "acc[s]"))))
     em.end()
+    if f32:
+        em("const double pf = s_q[jb * %d + %d];" % (NQ, 2 * N + 17))
+        em("#pragma unroll")
+        em("for (int s = 0; s < %d; ++s) acc[s] = fma((double)t[s], pf, acc[s]);" % S)
+        flops[0] += 2 * n
     em.end()
     em.end()
     flops[0] += 3 * N * n
@@ -1862,6 +1918,8 @@ HEADER = """// Generated by codegen.py -- class-specialised ERI kernels.
 TAG_DEFAULT, TAG_ALT, TAG_OCC2, TAG_TWO_WAVES, TAG_SWAP = 0, 1, 2, 3, 4
 TAG_TWO_WAVES_OCC2 = 5
 TAG_TWO_WAVES_XCOL_OCC2 = 6
+# workgroup Rys kernels (RYSW_VARIANTS): 7 larger batches; 8, 9 twice the threads at 4 or 2 waves per
+# SIMD; 10, 11, 12 the node loop not unrolled (at 1 and 2 waves per SIMD, and twice the threads at 2)
 
 
 def two_wave_form(cp):
@@ -1920,7 +1978,7 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     if classes is None:
         classes = [class_of(c) for c in range(256)]
     fp32_ok = mixed_fp32_classes()
-    jobs = [(c, prec) for prec in precisions if prec != "rys" for c in classes
+    jobs = [(c, prec) for prec in precisions if prec not in ("rys", "rys32") for c in classes
             if prec != "mixed" or class_id(*c) in fp32_ok]
     if g_classes:
         jobs += [(c, "fp64") for c in G_CLASSES]
@@ -2001,9 +2059,10 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
         fn = os.path.join(outdir, "eri_k%03d.hip" % (g // group))
         write_if_changed(fn, "\n".join(parts))
         files.append(fn)
-    if "rys" in precisions:
-        # Rys-quadrature kernels (classes with L_tot <= RYS_LMAX): one TU that
-        # alone includes the tables of the Rys rule
+    for rprec in [p_ for p_ in ("rys", "rys32") if p_ in precisions]:
+        # Rys-quadrature kernels (classes with L_tot <= RYS_LMAX, one lane per
+        # quartet): one TU that alone includes the tables of the Rys rule
+        real = REALS[rprec]
         parts = [HEADER, '#include "eri_rys.h"', '#include "eri_dispatch.h"']
         lines_ = []
         for user in classes:
@@ -2011,22 +2070,23 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 continue
             cp = plans.get(user) or ClassPlan(*user, **overrides.get(user, {}))
             plans[user] = cp
-            name = kernel_name("rys", cp.user)
-            _, src, fpq = emit_mode_R(cp, name)
+            name = kernel_name(rprec, cp.user)
+            _, src, fpq = emit_mode_R(cp, name, real)
             parts.append(src)
             pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
             c5 = class_id5(*user)
             for k, blk in enumerate((64, 128, 256)):
-                info = "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, %d, 0, 1}" % (
-                    name, blk, blk, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, TAG_DEFAULT)
+                info = "{(const void*)%s, 0, %d, %d, %d, %d, %d, %d, %d, %d, 1}" % (
+                    name, blk, blk, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, TAG_DEFAULT, int(real == "float"))
                 if k == 0:
                     lines_.append("    t[%d] = %s;" % (c5, info))
                 lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
-        parts.append("void eri_register_rys(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % "\n".join(lines_))
-        fn = os.path.join(outdir, "eri_rys.hip")
+        fname = "eri_register_%s" % rprec
+        parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
+        fn = os.path.join(outdir, "eri_%s.hip" % rprec)
         write_if_changed(fn, "\n".join(parts))
         files.append(fn)
-        regs.append(("rys", "eri_register_rys"))
+        regs.append((rprec, fname))
         # the larger classes: one workgroup per quartet, grouped by L_tot into
         # translation units of at most 24 classes
         big = sorted((u for u in classes if sum(u) > RYS_LMAX), key=lambda u: (sum(u), class_id(*u)))
@@ -2039,31 +2099,33 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
                 pk = cp.perm[0] | (cp.perm[1] << 2) | (cp.perm[2] << 4) | (cp.perm[3] << 6)
                 c5 = class_id5(*user)
                 k = 0
-                for (suffix, budget, occ), tag in zip(RYSW_VARIANTS, (TAG_DEFAULT, TAG_ALT, TAG_OCC2)):
-                    if k and rysw_shape(cp, budget) == rysw_shape(cp) and occ == 1:
+                vb = 4 if real == "float" else 8
+                for suffix, budget, occ, nts, unroll, tag in RYSW_VARIANTS:
+                    if budget != RYSW_LDS and rysw_shape(cp, budget, vb) == rysw_shape(cp, RYSW_LDS, vb):
                         continue   # the larger budget changes nothing for this class
-                    name = kernel_name("rys", cp.user) + suffix
-                    _, src, fpq = emit_mode_RW(cp, name, budget, occ)
+                    name = kernel_name(rprec, cp.user) + suffix
+                    _, src, fpq = emit_mode_RW(cp, name, budget, occ, real, nts, unroll)
                     parts.append(src)
-                    NT = rysw_shape(cp, budget)[0]
-                    info = "{(const void*)%s, 1, %d, 1, %d, %d, %d, %d, %d, 0, 0}" % (
-                        name, NT, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, tag)
+                    NT = rysw_shape(cp, budget, vb, nts)[0]
+                    info = "{(const void*)%s, 1, %d, 1, %d, %d, %d, %d, %d, %d, 0}" % (
+                        name, NT, cp.n_eriq, fpq, 3 * cp.n_eriq, pk, tag, int(real == "float"))
                     if k == 0:
                         lines_.append("    t[%d] = %s;" % (c5, info))
                     lines_.append("    v[%d] = %s;" % (c5 * MAXVAR + k, info))
                     k += 1
-            fname = "eri_register_rysw_g%02d" % (gi // 24)
+            fname = "eri_register_%sw_g%02d" % (rprec, gi // 24)
             parts.append("void %s(eri_kernel_info* t, eri_kernel_info* v)\n{\n%s\n}\n" % (fname, "\n".join(lines_)))
-            fn = os.path.join(outdir, "eri_rysw_g%02d.hip" % (gi // 24))
+            fn = os.path.join(outdir, "eri_%sw_g%02d.hip" % (rprec, gi // 24))
             write_if_changed(fn, "\n".join(parts))
             files.append(fn)
-            regs.append(("rys", fname))
+            regs.append((rprec, fname))
     lines = ['#include "eri_dispatch.h"', "#include <mutex>"]
     for prec, fname in regs:
         lines.append("void %s(eri_kernel_info* t, eri_kernel_info* v);" % fname)
-    lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5], g_rys[ERI_NCLASS5];")
+    lines.append("static eri_kernel_info g_fp64[ERI_NCLASS5], g_mixed[ERI_NCLASS5], g_rys[ERI_NCLASS5], "
+                 "g_rys32[ERI_NCLASS5];")
     lines.append("static eri_kernel_info v_fp64[ERI_NCLASS5 * ERI_MAXVAR], v_mixed[ERI_NCLASS5 * ERI_MAXVAR],")
-    lines.append("    v_rys[ERI_NCLASS5 * ERI_MAXVAR];")
+    lines.append("    v_rys[ERI_NCLASS5 * ERI_MAXVAR], v_rys32[ERI_NCLASS5 * ERI_MAXVAR];")
     lines.append("static std::once_flag g_once;")
     routed = [class_id5(*c) for c in classes if class_id(*c) not in fp32_ok] if "mixed" in precisions else []
     lines.append("// classes whose FP32-mixed entries are their FP64 kernels")
@@ -2083,12 +2145,12 @@ def generate(outdir, precisions=("fp64",), classes=None, group=8, overrides=None
     lines.append("const eri_kernel_info* eri_kernel_table(int precision)")
     lines.append("{")
     lines.append("    fill();")
-    lines.append("    return precision == 2 ? g_rys : precision == 1 ? g_mixed : g_fp64;")
+    lines.append("    return precision == 3 ? g_rys32 : precision == 2 ? g_rys : precision == 1 ? g_mixed : g_fp64;")
     lines.append("}")
     lines.append("const eri_kernel_info* eri_kernel_variants(int precision)")
     lines.append("{")
     lines.append("    fill();")
-    lines.append("    return precision == 2 ? v_rys : precision == 1 ? v_mixed : v_fp64;")
+    lines.append("    return precision == 3 ? v_rys32 : precision == 2 ? v_rys : precision == 1 ? v_mixed : v_fp64;")
     lines.append("}")
     fn = os.path.join(outdir, "eri_dispatch_table.hip")
     write_if_changed(fn, "\n".join(lines) + "\n")

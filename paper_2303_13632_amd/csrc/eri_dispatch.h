@@ -14,12 +14,15 @@ struct eri_kernel_info {
     int32_t tag;         // generated kernel: 0 default, 1 alternate mapping, 2 half-register (2 waves/SIMD),
                          // 3 two bra subslots on two wavefronts, 4 bra and ket exchanged, 5 two wavefronts
                          // at half the registers, 6 two wavefronts split by x-columns at half the
-                         // registers (the default of an f-f bra is the two-wavefront x-column form)
+                         // registers (the default of an f-f bra is the two-wavefront x-column form);
+                         // workgroup Rys kernels: 7 larger batches of primitive quartets, 8 twice the threads
+                         // at 4 waves per SIMD, 9 twice the threads at 2
     int32_t fp32;        // 1: VRR/HRR in FP32 (FP32-mixed kernel); 0: FP64
     int32_t pack_dyn;    // packed stream stages codes in dynamic LDS: 0 never, 1 always, 2 for n > 16
 };
 
-// Kernel table of a precision (0: FP64, 1: FP32-mixed, 2: Rys quadrature), indexed by
+// Kernel table of a precision (0: FP64, 1: FP32-mixed, 2: Rys quadrature, 3: Rys quadrature
+// with FP32 recurrences), indexed by
 // La*125 + Lb*25 + Lc*5 + Ld (angular momenta up to 4); entries of classes
 // without a kernel have fn == nullptr.  The FP32-mixed table holds FP64
 // kernels (fp32 == 0) for the classes whose FP32 recurrences miss 1e-7 Ha.

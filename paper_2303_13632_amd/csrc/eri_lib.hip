@@ -112,10 +112,10 @@ void build_pair_tables(const shell_set& s, const std::vector<uint64_t>& keys, st
 }
 
 
-// Index of a precision's kernel tables (0 FP64, 1 FP32-mixed, 2 Rys).
+// Index of a precision's kernel tables (0 FP64, 1 FP32-mixed, 2 Rys, 3 Rys with FP32 stages).
 static int table_index(int precision)
 {
-    return precision == ERI_RYS ? 2 : precision == ERI_FP32_MIXED ? 1 : 0;
+    return precision == ERI_RYS_FP32 ? 3 : precision == ERI_RYS ? 2 : precision == ERI_FP32_MIXED ? 1 : 0;
 }
 
 const eri_kernel_info* kernel_table(int precision)
@@ -495,9 +495,11 @@ extern "C" int eri_plan_create(eri_plan** out, int64_t n_shells, const int32_t* 
     const shell_set s{n_shells, L, K, xyz, prim_off, exps, coefs};
     int rc = check_shells(s);
     if (rc) return rc;
-    if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED && opts->precision != ERI_RYS)
+    if (opts->precision != ERI_FP64 && opts->precision != ERI_FP32_MIXED && opts->precision != ERI_RYS &&
+        opts->precision != ERI_RYS_FP32)
         return ERI_EUNSUPPORTED;
-    if (opts->precision == ERI_RYS && (opts->flags & ERI_PLAN_ALL_QUARTETS)) return ERI_EUNSUPPORTED;
+    if ((opts->precision == ERI_RYS || opts->precision == ERI_RYS_FP32) && (opts->flags & ERI_PLAN_ALL_QUARTETS))
+        return ERI_EUNSUPPORTED;
     if (opts->bits != 0 && (opts->bits < 2 || opts->bits > 32)) return ERI_EUNSUPPORTED;
     if (!(opts->schwarz_threshold >= 0.0) || opts->ring_bytes < 0 || opts->chunk_quartets < 0 ||
         opts->scale_block < 0)
@@ -942,7 +944,8 @@ extern "C" int eri_compute_class(eri_plan* p, int32_t c, void* stream, double* o
 static std::string tune_key(const eri_plan* p, int c)
 {
     char buf[64];
-    std::snprintf(buf, sizeof(buf), "%s:%d:%d", p->precision == ERI_RYS ? "rys" : p->precision == ERI_FP32_MIXED ? "mixed" : "fp64", c, p->bits);
+    static const char* const pname[] = {"fp64", "mixed", "rys", "rys32"};
+    std::snprintf(buf, sizeof(buf), "%s:%d:%d", pname[table_index(p->precision)], c, p->bits);
     return buf;
 }
 

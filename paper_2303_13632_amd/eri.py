@@ -22,7 +22,8 @@ ERI_ESTATE = -5
 ERI_FP64 = 0
 ERI_FP32_MIXED = 1
 ERI_RYS = 2
-PRECISIONS = {"fp64": ERI_FP64, "mixed": ERI_FP32_MIXED, "rys": ERI_RYS}
+ERI_RYS_FP32 = 3
+PRECISIONS = {"fp64": ERI_FP64, "mixed": ERI_FP32_MIXED, "rys": ERI_RYS, "rys32": ERI_RYS_FP32}
 
 _lib = None
 
@@ -228,8 +229,8 @@ class Plan:
 
     def kernel_name(self, cid):
         """Name of the kernel a class launch uses (variant included)."""
-        if self.precision == "rys":
-            return "eri_rys_c%03d" % cid
+        if self.precision in ("rys", "rys32"):
+            return "eri_%s_c%03d%s" % (self.precision, cid, KERNEL_TAG_SUFFIX[int(self.class_tag[cid])])
         prec = "mixed" if self.class_fp32[cid] else "fp64"
         return "eri_%s_c%03d%s" % (prec, cid, KERNEL_TAG_SUFFIX[int(self.class_tag[cid])])
 
@@ -376,7 +377,8 @@ class Plan:
 
 
 # Name suffix of the generated kernel of each variant tag (eri_plan_info.class_tag)
-KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2", 6: "_w2xo2"}
+KERNEL_TAG_SUFFIX = {0: "", 1: "_a", 2: "_o2", 3: "_w2", 4: "_s", 5: "_w2o2", 6: "_w2xo2", 7: "_b", 8: "_w", 9: "_wo2",
+                     10: "_n", 11: "_no2", 12: "_nwo2"}
 
 
 def _ncart(L):
