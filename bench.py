@@ -123,9 +123,9 @@ def main():
                          "int12 (12-bit codes packed into 512-bit words, pack kernel included), "
                          "fp64_out / int8 / int32 (same workload with FP64 output or 8-/32-bit codes), "
                          "gradient (fwd+grad on the 64-atom basis), molecule (every screened quartet of the "
-                         "384-atom molecule-like basis in one graph launch), rys (the Rys-quadrature kernels "
-                         "against the Obara-Saika ones on the classes with L_tot <= 4); 'none' for the headline "
-                         "only")
+                         "384-atom molecule-like basis in one graph launch), rys (the Rys-quadrature kernels, "
+                         "FP64 and with FP32 stages, against the Obara-Saika ones on every class, K~U{1,2,3} "
+                         "and K = 1); 'none' for the headline only")
     ap.add_argument("--per-class-out", default="", help="write per-class times/GERIS to this JSON file")
     ap.add_argument("--workload", default="classes", choices=["classes", "molecule", "gradient", "copy", "lattice"],
                     help="classes: 256 classes x quartets-per-class; molecule: every Schwarz-screened "
@@ -213,43 +213,50 @@ def main():
             if k in mol:
                 out["secondary"]["molecule"][k] = mol[k]
     if "rys" in sec and args.precision == "fp64":
-        out["secondary"]["rys"] = bench_rys(args)
+        out["secondary"]["rys"] = bench_rys(args, res)
     print(json.dumps(out), flush=True)
 
 
-def bench_rys(args):
-    """The Rys-quadrature kernels (FP64; one lane per quartet for L_tot <= 4,
-    one workgroup per quartet above) against the Obara-Saika/HGP kernels on
-    the same quartets of every class, both tuned, int16 codes: GERIS of each
-    and the per-class time ratio, on the workload (K~U{1,2,3}) and with one
-    primitive per shell (K = 1, where the paper expects Rys to need fewer
-    operations for high angular momenta)."""
+def bench_rys(args, os_workload=None):
+    """The Rys-quadrature kernels (one lane per quartet for L_tot <= 4, one
+    workgroup per quartet above; FP64, and with the paper's FP32 stages)
+    against the Obara-Saika/HGP kernels on the same quartets of every class,
+    all tuned, int16 codes: GERIS of each and the per-class time ratios, on
+    the workload (K~U{1,2,3}; the Obara-Saika figures are the headline run's
+    when given) and with one primitive per shell (K = 1, where the paper
+    expects Rys to need fewer operations for high angular momenta)."""
     from paper_2303_13632_amd import workloads as W
     classes = list(range(256))
     steps = max(1, args.steps // 2)
-    out = {}
-    for key, kf in (("workload", None), ("k1", 1)):
-        r = bench_classes(args, classes, "rys", args.bits, steps, 1, "", k_fixed=kf)
-        o = bench_classes(args, classes, "fp64", args.bits, steps, 1, "", k_fixed=kf)
+
+    def ratios(r, o):
         ratio = {c: r["per_class_ms"][c] / o["per_class_ms"][c] for c in r["per_class_ms"]}
         vals = sorted(ratio.values())
         by_l = {}
         for c, v in ratio.items():
             by_l.setdefault(sum(W.class_of(c)), []).append(v)
-        out[key] = {"value": r["geris"], "unit": "GERIS", "os_value": o["geris"], "n_classes": len(classes),
-                    "ms_per_step": r["ms_per_step"], "os_ms_per_step": o["ms_per_step"],
-                    "time_ratio_rys_over_os": {"min": vals[0], "median": vals[len(vals) // 2], "max": vals[-1],
-                                               "best_class": "[%d%d|%d%d]" % W.class_of(min(ratio, key=ratio.get)),
-                                               "median_by_L_tot": {str(k): float(np.median(v))
-                                                                   for k, v in sorted(by_l.items())}},
+        return {"min": vals[0], "median": vals[len(vals) // 2], "max": vals[-1],
+                "best_class": "[%d%d|%d%d]" % W.class_of(min(ratio, key=ratio.get)),
+                "median_by_L_tot": {str(k): round(float(np.median(v)), 3) for k, v in sorted(by_l.items())}}
+    out = {}
+    for key, kf in (("workload", None), ("k1", 1)):
+        o = os_workload if (kf is None and os_workload is not None) else \
+            bench_classes(args, classes, "fp64", args.bits, steps, 1, "", k_fixed=kf)
+        r = bench_classes(args, classes, "rys", args.bits, steps, 1, "", k_fixed=kf)
+        r32 = bench_classes(args, classes, "rys32", args.bits, steps, 1, "", k_fixed=kf)
+        out[key] = {"value": r["geris"], "unit": "GERIS", "fp32_stages_value": r32["geris"], "os_value": o["geris"],
+                    "n_classes": len(classes), "ms_per_step": r["ms_per_step"],
+                    "fp32_stages_ms_per_step": r32["ms_per_step"], "os_ms_per_step": o["ms_per_step"],
+                    "time_ratio_rys_over_os": ratios(r, o), "time_ratio_rys_fp32_stages_over_os": ratios(r32, o),
                     "roofline_class": r["roofline"]["class"], "roofline_kernel": r["roofline"]["kernel"],
                     "roofline_frac": r["roofline"]["frac"], "whole_step_tflops": r["whole_step_tflops"],
                     "config": r["config"]["workload"]}
     res = dict(out["workload"])
     res["k1"] = out["k1"]
-    res["note"] = ("every class, %d quartets each; the Rys FLOP count (node/weight series, 2D recurrences "
-                   "and transfers per node and axis, three products per ERI and node) is its own"
-                   % args.quartets_per_class)
+    res["note"] = ("every class, %d quartets each; value = Rys in FP64, fp32_stages_value = Rys with FP32 "
+                   "recurrences, transfers and node sums (FP64 rule, prefactor, contraction); the Rys FLOP count "
+                   "(node/weight series, 2D recurrences and transfers per node and axis, three products per ERI "
+                   "and node) is its own" % args.quartets_per_class)
     return res
 
 

@@ -16,7 +16,8 @@ struct eri_kernel_info {
                          // at half the registers, 6 two wavefronts split by x-columns at half the
                          // registers (the default of an f-f bra is the two-wavefront x-column form);
                          // workgroup Rys kernels: 7 larger batches of primitive quartets, 8 twice the threads
-                         // at 4 waves per SIMD, 9 twice the threads at 2
+                         // at 4 waves per SIMD, 9 twice the threads at 2; 10, 11, 12 the node loop not
+                         // unrolled (1 and 2 waves per SIMD, twice the threads at 2)
     int32_t fp32;        // 1: VRR/HRR in FP32 (FP32-mixed kernel); 0: FP64
     int32_t pack_dyn;    // packed stream stages codes in dynamic LDS: 0 never, 1 always, 2 for n > 16
 };

@@ -85,6 +85,10 @@ def test_kernel_tag_suffixes_match_generator():
     G = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(G)
     tags = {v: k for k, v in vars(G).items() if k.startswith("TAG_") and isinstance(v, int)}
+    # the workgroup Rys kernels' variants carry their tags and suffixes in one table
+    for suffix, _, _, _, _, tag in G.RYSW_VARIANTS:
+        assert eri.KERNEL_TAG_SUFFIX[tag] == suffix, (tag, suffix)
+        tags.setdefault(tag, suffix)
     assert set(tags) == set(eri.KERNEL_TAG_SUFFIX)
     # generated names: default, half-register and alternate forms of [ff|df]
     cp = G.ClassPlan(3, 3, 2, 3)
