@@ -270,7 +270,8 @@ int eri_decompress(int32_t bits, const void* codes, const double* scales, int64_
  * density, the degeneracy of the unique quartet (2 for a != b, 2 for c != d,
  * 2 for (ab) != (cd)), so that L = sum_(mu nu lam sig) D D (mu nu|lam sig).
  * Exactly one of dl_deri and density is given.  The call ADDS dL/dR to
- * grad_centers (device, 3 per shell, the shell's centre xyz) and dL/dalpha to
+ * grad_centers (device, 3 per shell, the shell's centre xyz: an atom's gradient
+ * is the sum over its shells) and dL/dalpha to
  * grad_exps (device, one per primitive, indexed like exps: prim_off[s] + k),
  * and L itself to *energy (device, optional).  With grad_centers and grad_exps
  * both NULL only L is computed (energy then required).  The coefficients are
