@@ -916,7 +916,7 @@ def emit_kx(em, cp):
         em("const int64_t kx = %s;" % kn)
 
 
-def emit_pack_regs(em, cp, n, step, lane, guard, staged, ab_list, stage_base):
+def emit_pack_regs(em, cp, n, step, lane, guard, staged, ab_list, stage_base, coefs=None):
     """Codes of a single-chunk slot kernel's packed path: the bra HRR of every
     ket index this lane owns (j = lane, lane + step, ...) is quantised into
     registers (fast multiply-by-reciprocal quantiser unless some 1/eps of the
@@ -931,6 +931,8 @@ def emit_pack_regs(em, cp, n, step, lane, guard, staged, ab_list, stage_base):
         em.block("for (int it = 0; it < %d; ++it)" % NIT)
         em("const int j = %s + it * %d;" % (lane, step))
         em.block("if (%sj < %d)" % (guard, n))
+        if coefs is not None:
+            coefs()
         for k, (ai, bi) in enumerate(ab_list):
             expr = hrr_expr(bi, ai, staged, "ab")
             q = ("eri_quantize_mul((double)(%s), inv, A.qmax)" if fast else
@@ -1375,8 +1377,16 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
     # HRR
     emit_slot(em, "qi")
     em("const int64_t obase = oslot * %d;" % cp.n_eriq)
-    emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
-    emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
+    # HRR coefficients: at half the registers (waves > 1) they are formed where
+    # they are used (the same products each time, so every pass sees the same
+    # bits), since declared once for the epilogue they stayed live and spilled
+    # (e.g. [ff|dd] 772 -> 548 bytes per lane, 2.7% faster); at full registers
+    # the one declaration spills little ([ff|ff] 164 bytes) and forming them per
+    # use measured 3.5% slower
+    per_use = waves > 1
+    if not per_use:
+        emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
+        emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
     cd_list = [(ci, di) for ci in cc for di in cd]
     ab_list = [(ai, bi) for ai in ca for bi in cb]
 
@@ -1386,6 +1396,8 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
         em("__syncthreads();")
         for s in range(S):
             em.block("if (active && tg%d >= 0)" % s)
+            if per_use:
+                emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
             for k in range(lo, hi):
                 ci, di = cd_list[k]
                 expr = hrr_expr(di, ci, lambda f, s=s: "(%s)%s" % (real, acc[(s, f)]), "cd")
@@ -1401,10 +1413,13 @@ def emit_mode_W(cp, prec, name, lds_budget=None, waves=1):
         n = hi - lo
         if pass_no == 4:
             emit_pack_regs(em, cp, n, EP, "ls", "active && ",
-                           lambda e: "(%s)%s[slot][%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base)
+                           lambda e: "(%s)%s[slot][%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base,
+                           (lambda: emit_hrr_coefs(em, "ab", "BP.AB", cb, real)) if per_use else None)
             return
         em.block("for (int j = ls; j < %d; j += %d)" % (n, EP))
         em.block("if (active)")
+        if per_use:
+            emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
         em("const int kcd = %d + j;" % lo)
         for k, (ai, bi) in enumerate(ab_list):
             expr = hrr_expr(bi, ai, lambda e: "(%s)%s[slot][%d][j]" % (real, st, tgt_index[e]), "ab")
@@ -1736,8 +1751,16 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
     # HRR: ket per lane into s_t rows, bra over all 128 threads
     emit_slot(em, "qi")
     em("const int64_t obase = oslot * %d;" % cp.n_eriq)
-    emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
-    emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
+    # HRR coefficients: at half the registers (waves > 1) they are formed where
+    # they are used (the same products each time, so every pass sees the same
+    # bits), since declared once for the epilogue they stayed live and spilled
+    # (e.g. [ff|dd] 772 -> 548 bytes per lane, 2.7% faster); at full registers
+    # the one declaration spills little ([ff|ff] 164 bytes) and forming them per
+    # use measured 3.5% slower
+    per_use = waves > 1
+    if not per_use:
+        emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
+        emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
     cd_list = [(ci, di) for ci in cc for di in cd]
     ab_list = [(ai, bi) for ai in ca for bi in cb]
 
@@ -1746,6 +1769,8 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
         lo, hi = ch * CH, min(NCD, (ch + 1) * CH)
         em("__syncthreads();")
         em.block("if (active && tg0 >= 0)")
+        if per_use:
+            emit_hrr_coefs(em, "cd", "KP.AB", cd, real)
         for k in range(lo, hi):
             ci, di = cd_list[k]
             expr = hrr_expr(di, ci, lambda f: "(%s)%s" % (real, acc[f]), "cd")
@@ -1761,10 +1786,13 @@ def emit_mode_W2(cp, prec, name, lds_budget=None, waves=1, layout="parity"):
         n = hi - lo
         if pass_no == 4:
             emit_pack_regs(em, cp, n, 128, "tid", "active && ",
-                           lambda e: "(%s)%s[%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base)
+                           lambda e: "(%s)%s[%d][j]" % (real, st, tgt_index[e]), ab_list, stage_base,
+                           (lambda: emit_hrr_coefs(em, "ab", "BP.AB", cb, real)) if per_use else None)
             return
         em.block("for (int j = tid; j < %d; j += 128)" % n)
         em.block("if (active)")
+        if per_use:
+            emit_hrr_coefs(em, "ab", "BP.AB", cb, real)
         em("const int kcd = %d + j;" % lo)
         for k, (ai, bi) in enumerate(ab_list):
             expr = hrr_expr(bi, ai, lambda e: "(%s)%s[%d][j]" % (real, st, tgt_index[e]), "ab")
