@@ -205,3 +205,31 @@ def test_rys_fp32_stages_on_the_paper_lattice():
           "max %.2e Ha against the oracle (paper's 16-bit range: up to %.0e Ha)"
           % (worst_fp32, worst_half, worst_dec, facts["decompressed_error_16bit_Ha"]["max"]), flush=True)
     assert worst_dec <= top, worst_dec
+
+
+@pytest.mark.parametrize("precision", ["rys", "rys32"])
+def test_rys_scale_blocks(precision):
+    """Scale blocks of G = 64 quartets (eq. 9 over the block) with the Rys
+    kernels, lane and workgroup classes: codes and scales bit-identical to the
+    oracle's compressor fed the kernels' doubles over the same blocks."""
+    from paper_2303_13632_amd import eri
+    parts = [W.class_case(cid, n_quartets=150, seed=W.SEED_BASE + 98) for cid in (5, 85, 170, 238, 255)]
+    shells, quartets = W.merge(parts)
+    G = 64
+    plan = eri.Plan(shells, quartets, precision=precision, bits=16, scale_block=G)
+    assert plan.scale_block == G
+    e, c, s = plan.alloc(eri=True, codes=True)
+    plan.compute(e, c, s)
+    torch.cuda.synchronize()
+    vals = e.cpu().numpy()[: plan.n_eri]
+    off = []
+    for cid in range(256):
+        n = int(plan.class_quartets[cid])
+        if n:
+            m = int((plan.class_eri_off[cid + 1] - plan.class_eri_off[cid]) // n)
+            off.append(plan.class_eri_off[cid] + m * np.arange(0, n, G))
+    blk = np.concatenate(off + [[plan.n_eri]]).astype(np.int64)
+    assert plan.out_blocks == len(blk) - 1
+    oc, oe = O.compress(16, vals, blk)
+    assert np.array_equal(oe, s.cpu().numpy()[: plan.out_blocks])
+    assert np.array_equal(oc, c.cpu().numpy()[: plan.n_eri].astype(np.int32))
