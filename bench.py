@@ -724,7 +724,10 @@ def fd_check(plan, D, gc, ge, args, h=1e-4):
             "max_rel_richardson": max(r["rel_richardson"] for r in rows),
             "n_rel_above_1e-6": int(sum(r["rel"] > 1e-6 for r in rows)),
             "max_abs_over_gmax": max(abs(r["fd"] - r["analytic"]) for r in rows) / gmax,
-            "worst": max(rows, key=lambda r: r["rel"])}
+            "max_abs_over_gmax_richardson": max(abs(r["fd_richardson"] - r["analytic"]) for r in rows) / gmax,
+            "n_rel_richardson_above_1e-6": int(sum(r["rel_richardson"] > 1e-6 for r in rows)),
+            "worst": max(rows, key=lambda r: r["rel"]),
+            "worst_richardson": max(rows, key=lambda r: r["rel_richardson"]), "gmax": float(gmax)}
 
 
 if __name__ == "__main__":
