@@ -246,7 +246,7 @@ def test_config5_sample_vs_oracle():
     L = sh["L"]
     assert any(all(L[s] == 2 for s in q) for q in qs)
     assert max(sh["K"][s] for q in qs for s in q) == 6
-    print("config-5 sample: %d quartets" % len(qs), flush=True)
+    print("64-atom basis sample: %d screened quartets" % len(qs), flush=True)
     plan = eri.Plan(sh, qs, bits=0)
     D = W.random_density(plan.nbf)
     w = _unique_weights(qs)
